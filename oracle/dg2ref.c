@@ -217,7 +217,7 @@ static void pass_limit(dg2ref_ctx *c, const double *S, double *out) {
         c->flat[k] = 1;
         continue;
       }
-      if (!c->cfg.limiter) continue;
+      if (c->cfg.limiter)
       for (int d = 1; d <= 2; ++d) {
         size_t km, kp; /* neighbours in direction d, the cell itself at an edge */
         if (d == 1) {
@@ -240,6 +240,19 @@ static void pass_limit(dg2ref_ctx *c, const double *S, double *out) {
           double a0 = S[PL(var, 0) * n + k];
           double am = S[PL(var, 0) * n + km], ap = S[PL(var, 0) * n + kp];
           out[PL(var, d) * n + k] = minmod3(S[PL(var, d) * n + k], (ap - a0) / SQRT3, (a0 - am) / SQRT3);
+        }
+      }
+      /* a depth plane that is negative at a face centre marks a wet/dry front inside
+         the cell: it is made first order like the front cells above */
+      {
+        const double h0 = out[PL(0, 0) * n + k];
+        const double ax = SQRT3 * fabs(out[PL(0, 1) * n + k]), ay = SQRT3 * fabs(out[PL(0, 2) * n + k]);
+        if (h0 - ax < 0.0 || h0 - ay < 0.0) {
+          for (int var = 0; var < 3; ++var) {
+            out[PL(var, 1) * n + k] = 0.0;
+            out[PL(var, 2) * n + k] = 0.0;
+          }
+          c->flat[k] = 1;
         }
       }
     }
@@ -310,6 +323,28 @@ void dg2ref_hll(double g, double hL, double unL, double utL, double hR, double u
     out[m] = (sR * FL[m] - sL * FR[m] + sL * sR * (UR[m] - UL[m])) / (sR - sL);
 }
 
+/* mean velocity of a cell, zero at or below h_tol */
+static double mean_vel(const double *S, size_t n, size_t k, int var, double ht) {
+  double h0 = S[PL(0, 0) * n + k];
+  return h0 > ht ? S[PL(var, 0) * n + k] / h0 : 0.0;
+}
+
+static double capd(double x, double a, double b, double slack) {
+  double m = (fabs(a) > fabs(b) ? fabs(a) : fabs(b)) + slack;
+  return x > m ? m : (x < -m ? -m : x);
+}
+
+/* Reading: each velocity component of a face limit is capped in magnitude by the
+ * larger magnitude of that component's mean velocity in the two cells sharing the
+ * face (a cell across a boundary face counts as a copy of the interior cell), plus
+ * sqrt(g h_tol), the velocity scale of the dry tolerance. Depth and discharge planes
+ * are limited separately, so where the depth plane nears zero at a face their ratio
+ * is otherwise unbounded. */
+static void clamp_side(side_t *s, double ua, double va, double ub, double vb, double slack) {
+  s->u = capd(s->u, ua, ub, slack);
+  s->v = capd(s->v, va, vb, slack);
+}
+
 /* inflow hydrograph Q(t): piecewise linear between knots, held beyond the ends */
 static double hydro(const seg_t *s, double t) {
   int n = s->n_knots;
@@ -361,6 +396,7 @@ static void pass_faces(dg2ref_ctx *c, const double *S, double t, double *in_rate
   const int nx = c->nx, ny = c->ny;
   const size_t n = c->n;
   const double g = c->cfg.g, ht = c->cfg.h_tol;
+  const double slack = sqrt(g * ht);
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int f = 0; f <= nx; ++f) {
@@ -385,6 +421,13 @@ static void pass_faces(dg2ref_ctx *c, const double *S, double t, double *in_rate
         double qx = S[PL(1, 0) * n + k] - SQRT3 * S[PL(1, 1) * n + k];
         double qy = S[PL(2, 0) * n + k] - SQRT3 * S[PL(2, 1) * n + k];
         fc->hi = revise(h, qx, qy, zr, zs, ht);
+      }
+      {
+        size_t ka = f > 0 ? kl : kr, kb = f < nx ? kr : kl;
+        double ua = mean_vel(S, n, ka, 1, ht), va = mean_vel(S, n, ka, 2, ht);
+        double ub = mean_vel(S, n, kb, 1, ht), vb = mean_vel(S, n, kb, 2, ht);
+        if (f > 0) clamp_side(&fc->lo, ua, va, ub, vb, slack);
+        if (f < nx) clamp_side(&fc->hi, ua, va, ub, vb, slack);
       }
       double gh, gu, gv;
       if (f == 0) {
@@ -421,6 +464,13 @@ static void pass_faces(dg2ref_ctx *c, const double *S, double t, double *in_rate
         double qx = S[PL(1, 0) * n + k] - SQRT3 * S[PL(1, 2) * n + k];
         double qy = S[PL(2, 0) * n + k] - SQRT3 * S[PL(2, 2) * n + k];
         fc->hi = revise(h, qx, qy, zr, zs, ht);
+      }
+      {
+        size_t ka = f > 0 ? kl : kr, kb = f < ny ? kr : kl;
+        double ua = mean_vel(S, n, ka, 1, ht), va = mean_vel(S, n, ka, 2, ht);
+        double ub = mean_vel(S, n, kb, 1, ht), vb = mean_vel(S, n, kb, 2, ht);
+        if (f > 0) clamp_side(&fc->lo, ua, va, ub, vb, slack);
+        if (f < ny) clamp_side(&fc->hi, ua, va, ub, vb, slack);
       }
       double gh, gn, gt;
       if (f == 0) {
@@ -569,9 +619,11 @@ static double pass_cleanup(dg2ref_ctx *c, double *S, int *bad) {
 
 /* ------------------------------------------------------------------------------ */
 /* CFL time step (Sect. 2.1.1, Courant number 0.33). Reading: over cells with       */
-/* h0 > h_tol, dx / (|u0| + sqrt(g h0)) per direction; boundary forcing (the        */
-/* critical-depth inflow state, a fixed state) also bounds it; dt_dry if nothing    */
-/* does.                                                                            */
+/* h0 > h_tol, dx / (|u0| + sqrt(g h)) per direction with the mean velocity u0 and  */
+/* the largest depth among the mean and the two face-centre limits in that          */
+/* direction (face velocities never exceed the neighbouring mean velocities, see    */
+/* the revision); boundary forcing (the critical-depth inflow state, a fixed state) */
+/* also bounds it; dt_dry if nothing does.                                          */
 /* ------------------------------------------------------------------------------ */
 static double cfl_dt(const dg2ref_ctx *c, const double *S, double t) {
   const size_t n = c->n;
@@ -580,11 +632,13 @@ static double cfl_dt(const dg2ref_ctx *c, const double *S, double t) {
   for (size_t k = 0; k < n; ++k) {
     double h0 = S[PL(0, 0) * n + k];
     if (!(h0 > ht)) continue;
-    double u = S[PL(1, 0) * n + k] / h0, v = S[PL(2, 0) * n + k] / h0;
-    double cw = sqrt(g * h0);
-    double a = dx / (fabs(u) + cw), b = dx / (fabs(v) + cw);
-    if (a < m) m = a;
-    if (b < m) m = b;
+    for (int d = 1; d <= 2; ++d) { /* d = 1: x (velocity qx0/h0), d = 2: y (qy0/h0) */
+      double h1 = SQRT3 * fabs(S[PL(0, d) * n + k]);
+      double hmax = h0 + h1;
+      double u = S[PL(d, 0) * n + k] / h0;
+      double a = dx / (fabs(u) + sqrt(g * hmax));
+      if (a < m) m = a;
+    }
   }
   for (int s = 0; s < c->n_segs; ++s) {
     const seg_t *sg = &c->segs[s];
