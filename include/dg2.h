@@ -1,0 +1,181 @@
+/*
+ * dg2.h -- C interface of the MI355X (gfx950) library for the uniform-grid DG2 time
+ * step of the 2D shallow water equations (Sharifian & Kesserwani, arXiv:2107.02750).
+ *
+ * The operation: the flood-model statement of Sect. 2.1 -- a raster DEM at resolution
+ * R = dx = dy, Manning's n, an initial condition given as a raster, inflow hydrographs
+ * at the boundary -- advanced by the second-order discontinuous Galerkin (DG2) scheme
+ * of Sect. 2.1.1: piecewise-planar coefficients of h, qx, qy (eq 2) over a
+ * piecewise-planar bed projected from the DEM vertices (eq 3, eq 8), a two-stage RK2
+ * update (eq 4) of the spatial operator L with HLL fluxes at the four face centres
+ * after wet/dry and well-balancing revisions, split-implicit Manning friction at the
+ * start of each step, and a global CFL time step with Courant number 0.33.
+ *
+ * Conventions
+ *  - All calls return int: DG2_OK (0) or a negative DG2_E_* code. No C++ exception
+ *    crosses this interface. After an error on a context, dg2_last_error() describes
+ *    it; after a failed dg2_init, dg2_init_error() does.
+ *  - Grid: cells (i, j), i = 0..nx-1 west to east, j = 0..ny-1 south to north.
+ *    Cell rasters are nx*ny values, row-major, cell (i, j) at index j*nx + i.
+ *    Vertex rasters are (nx+1)*(ny+1) values, vertex (i, j) at j*(nx+1) + i; cell
+ *    (i, j) has SW = (i, j), SE = (i+1, j), NW = (i, j+1), NE = (i+1, j+1).
+ *  - Coefficient planes (eq 2), in this order: h0, h1x, h1y, qx0, qx1x, qx1y, qy0,
+ *    qy1x, qy1y (index 3*var + k, var = h, qx, qy; k = mean, x-slope, y-slope).
+ *  - Precision: DG2_FP64 computes and stores everything in double; DG2_FP32 computes
+ *    and stores the coefficients and the bed in float, while time, the time step and
+ *    the mass ledger stay in double. "real" below is the context's precision.
+ *  - Memory: the caller owns every input; host inputs are copied during dg2_init and
+ *    may be freed afterwards. The caller allocates the device workspace (its size from
+ *    dg2_workspace_size) and keeps it alive, untouched, until dg2_destroy. The library
+ *    owns the context. The HIP stream is borrowed: every kernel and copy of a context
+ *    is issued on it, in order. A context is not thread-safe; use one per stream.
+ *  - Units: metres, seconds, m^3/s for hydrographs.
+ */
+#ifndef DG2_H
+#define DG2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DG2_OK = 0,
+  DG2_E_ARG = -1,        /* bad argument; nothing was changed */
+  DG2_E_DEVICE = -2,     /* a HIP call failed (message names it) */
+  DG2_E_NUMERIC = -3,    /* NaN in the state, or the time step fell below 1e-12 s */
+  DG2_E_STATE = -4,      /* state blob of the wrong size, precision or grid */
+  DG2_E_UNSUPPORTED = -5 /* valid request this build does not support */
+};
+
+enum { DG2_FP64 = 0, DG2_FP32 = 1 };
+
+/* boundary kinds. Transmissive: the ghost state copies the interior face state. Wall:
+ * the normal velocity is reflected. Fixed: (h_b, u_b, v_b) is imposed. Inflow: a
+ * hydrograph Q(t) spread evenly over the segment's faces enters at the larger of the
+ * interior depth and the critical depth of that unit discharge (Sect. 3.1-3.3: inflow
+ * hydrographs imposed near the domain edge; the paper gives no formula). */
+enum { DG2_BC_TRANSMISSIVE = 0, DG2_BC_WALL = 1, DG2_BC_FIXED = 2, DG2_BC_INFLOW = 3 };
+enum { DG2_EDGE_W = 0, DG2_EDGE_E = 1, DG2_EDGE_S = 2, DG2_EDGE_N = 3 };
+
+/* initial-condition modes (Sect. 2.1.4: flow coefficients are initialised from a
+ * raster in the same way as the bed) */
+enum {
+  DG2_INIT_PLANES = 0, /* init_data: 9 coefficient planes, nx*ny doubles each */
+  DG2_INIT_MEANS = 1,  /* init_data: 3 cell rasters h, qx, qy (means; zero slopes) */
+  DG2_INIT_VERTEX = 2, /* init_data: 3 vertex rasters h, qx, qy, projected as eq 8 */
+  DG2_INIT_LEVEL = 3   /* still water at eta_level: h0 = eta - z0, h1 = -z1 where
+                          h0 > 0, dry elsewhere; init_data unused */
+};
+
+/* limits of the boundary table */
+#define DG2_MAX_SEGMENTS 64
+#define DG2_MAX_KNOTS 8192 /* total over all inflow segments */
+
+typedef struct {
+  int32_t nx, ny;          /* cells, >= 1 each */
+  double dx;               /* R = dx = dy, > 0 */
+  double g;                /* gravity, > 0 (9.80665) */
+  double cfl;              /* Courant number, > 0 (0.33, Sect. 2.1.1) */
+  double h_tol;            /* dry tolerance, >= 0 (1e-3) */
+  double dt_dry;           /* time step when no wet cell and no forcing bounds it, > 0 */
+  double t0;               /* initial time */
+  int32_t precision;       /* DG2_FP64 or DG2_FP32 */
+  int32_t limiter;         /* 1: minmod on eta, qx, qy; 0: off (fronts stay first order) */
+  int32_t edge_kind[4];    /* default kind of each edge W, E, S, N: transmissive or wall */
+} dg2_config;
+
+typedef struct {
+  int32_t edge;            /* DG2_EDGE_* */
+  int32_t kind;            /* DG2_BC_* */
+  int32_t i0, i1;          /* faces [i0, i1) along the edge: j for W/E, i for S/N */
+  int32_t n_knots;         /* inflow: number of hydrograph knots (>= 1) */
+  const double *t_knots;   /* inflow: strictly increasing times (host memory) */
+  const double *q_knots;   /* inflow: Q >= 0 at the knots; linear between, held
+                              constant before the first and after the last */
+  double h_b, u_b, v_b;    /* fixed: imposed depth (>= 0) and velocity */
+} dg2_boundary;
+
+typedef struct dg2_ctx dg2_ctx;
+
+/* Device workspace bytes a context with this configuration needs (256-byte aligned
+ * base required). Errors: DG2_E_ARG for a NULL pointer, a grid below 1x1 or an unknown
+ * precision. */
+int dg2_workspace_size(const dg2_config *cfg, size_t *bytes);
+
+/* Create a context: validate the inputs on the host, copy them to the workspace on
+ * `hip_stream` (a hipStream_t; NULL = the default stream), project the bed (eq 8) and
+ * the initial state on the GPU, and compute the first CFL time step.
+ *  z_vertices: (nx+1)*(ny+1) host doubles, finite.
+ *  manning: nx*ny host doubles >= 0, or NULL to use manning_scalar everywhere.
+ *  init_mode / init_data / eta_level: see DG2_INIT_*; depths must be >= 0. Discharge
+ *    in cells whose mean depth is <= h_tol is set to zero.
+ *  bcs / n_bcs: up to DG2_MAX_SEGMENTS segments; faces not covered use the edge default.
+ *  d_workspace / ws_bytes: device memory of at least dg2_workspace_size bytes.
+ * On success *out is the new context; on failure *out is NULL and nothing is kept.
+ * Errors: DG2_E_ARG (bad sizes, non-finite or negative values, overlapping or
+ * out-of-range segments, unsorted knots, small workspace), DG2_E_DEVICE. */
+int dg2_init(const dg2_config *cfg, const double *z_vertices, const double *manning,
+             double manning_scalar, int32_t init_mode, const double *init_data,
+             double eta_level, const dg2_boundary *bcs, int32_t n_bcs, void *d_workspace,
+             size_t ws_bytes, void *hip_stream, dg2_ctx **out);
+
+/* Enqueue one time step (friction, then the two RK2 stages of eq 4) with
+ * dt = min(CFL dt, dt_max) (dt_max <= 0: no cap). The step's dt is found on the GPU;
+ * with dt_used == NULL the call does not wait for the GPU. With dt_used != NULL it
+ * waits and returns the dt taken, and reports DG2_E_NUMERIC if the health flag is set.
+ */
+int dg2_step(dg2_ctx *c, double dt_max, double *dt_used);
+
+/* Step until t == t_end exactly (the last step is shortened). Waits for the GPU.
+ * *steps_taken (may be NULL) receives the number of steps. Errors: DG2_E_ARG if
+ * t_end is before the current time, DG2_E_NUMERIC (state left at the failing step). */
+int dg2_run(dg2_ctx *c, double t_end, int64_t *steps_taken);
+
+/* Copy one field of the current state to dst (nx*ny values of the context's real type):
+ * 0..8 the coefficient planes, 9 eta0 = h0 + z0, 10 u0 = qx0/h0, 11 v0 = qy0/h0 (0
+ * where h0 <= h_tol). dst is device memory if dst_is_device, else host memory. Waits
+ * for the GPU. */
+int dg2_read(dg2_ctx *c, int32_t field, void *dst, int32_t dst_is_device);
+
+/* Time, step count, stored mass sum(h0) dx^2 (computed now, FP64) and the FP64 mass
+ * ledger: boundary inflow, boundary outflow and mass added by clipping negative mean
+ * depths, so that mass - mass(t0) == mass_in - mass_out + mass_clip up to round-off.
+ * Any pointer may be NULL. Waits for the GPU. */
+int dg2_get_scalars(dg2_ctx *c, double *t, int64_t *step, double *mass, double *mass_in,
+                    double *mass_out, double *mass_clip);
+
+/* The CFL time step (before any cap) that the next step would take. Waits. */
+int dg2_next_dt(dg2_ctx *c, double *dt);
+
+/* Checkpoint / resume: an opaque host blob with the coefficient planes, time, step,
+ * next time step and ledger. dg2_set_state accepts only a blob from a context of the
+ * same grid, precision and tile layout (else DG2_E_STATE). Both wait. */
+int dg2_state_bytes(const dg2_ctx *c, size_t *bytes);
+int dg2_get_state(dg2_ctx *c, void *host_dst);
+int dg2_set_state(dg2_ctx *c, const void *host_src);
+
+/* Per-kernel timing with HIP events on the context's stream. While enabled, every
+ * stage kernel launch is bracketed by events; dg2_get_timing waits and returns the
+ * number of timed steps and the mean milliseconds per launch of the stage-1 and
+ * stage-2 kernels since timing was (re)enabled. */
+int dg2_set_timing(dg2_ctx *c, int32_t on);
+int dg2_get_timing(dg2_ctx *c, int64_t *steps, double *ms_stage1, double *ms_stage2);
+
+/* Launch geometry of the stage kernels (for the roofline accounting): tile width and
+ * height in cells, threads per block, blocks per launch, LDS bytes per block. */
+int dg2_kernel_info(const dg2_ctx *c, int32_t *tile_x, int32_t *tile_y, int32_t *threads,
+                    int32_t *blocks, int32_t *lds_bytes);
+
+const char *dg2_last_error(const dg2_ctx *c);
+const char *dg2_init_error(void);
+
+/* Release the context (waits for its stream). The workspace is the caller's. */
+void dg2_destroy(dg2_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG2_H */

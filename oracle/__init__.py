@@ -68,6 +68,8 @@ def load():
     lib.dg2ref_bed_coeffs.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]
     lib.dg2ref_bed_coeffs.restype = None
     lib.dg2ref_operator.argtypes = [vp, _dp, C.c_double, _dp, _dp, _dp]
+    lib.dg2ref_threads.argtypes = []
+    lib.dg2ref_threads.restype = C.c_int
     lib.dg2ref_limit.argtypes = [vp, _dp, _dp]
     _lib = lib
     return lib
@@ -202,3 +204,8 @@ def bed_coeffs(zv: np.ndarray):
     z0, z1x, z1y = (np.empty((ny, nx)) for _ in range(3))
     load().dg2ref_bed_coeffs(nx, ny, _ptr(zv), _ptr(z0), _ptr(z1x), _ptr(z1y))
     return z0, z1x, z1y
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's passes run on."""
+    return int(load().dg2ref_threads())

@@ -953,3 +953,14 @@ int dg2ref_set_state(dg2ref_ctx *c, const double *src) {
 }
 
 const char *dg2ref_last_error(const dg2ref_ctx *c) { return c ? c->err : "no context"; }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int dg2ref_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

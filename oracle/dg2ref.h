@@ -81,6 +81,8 @@ const char *dg2ref_last_error(const dg2ref_ctx *c);
 /* message of the last failed dg2ref_init */
 const char *dg2ref_init_error(void);
 void dg2ref_destroy(dg2ref_ctx *c);
+/* number of OpenMP threads the passes use */
+int dg2ref_threads(void);
 
 /* ---- pieces exposed for unit pins ---- */
 /* HLL flux across a face with normal n: states (h, u_n, u_t) left and right;

@@ -1,0 +1,625 @@
+// dg2.hip -- host side of the C interface declared in include/dg2.h: argument checks,
+// workspace layout, launches on the borrowed stream, and state transfer. The kernels
+// are in dg2_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dg2.h"
+#include "dg2_kernels.hpp"
+
+using dg2k::Ctrl;
+using dg2k::Params;
+using dg2k::Seg;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  size_t u0, u1, ui, zv, man, bface, segs, knots, ctrl, ledger, scal, total;
+  int tiles_x, tiles_y, n_tiles, per_xcd, grid;
+};
+
+Layout layout(const dg2_config& c) {
+  Layout L{};
+  const size_t n = (size_t)c.nx * c.ny;
+  const size_t rs = c.precision == DG2_FP32 ? 4 : 8;
+  L.tiles_x = (c.nx + dg2k::TX - 1) / dg2k::TX;
+  L.tiles_y = (c.ny + dg2k::TY - 1) / dg2k::TY;
+  L.n_tiles = L.tiles_x * L.tiles_y;
+  L.per_xcd = (L.n_tiles + dg2k::NXCD - 1) / dg2k::NXCD;
+  L.grid = L.per_xcd * dg2k::NXCD;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = up(off + bytes);
+    return o;
+  };
+  L.u0 = take(9 * n * rs);
+  L.u1 = take(9 * n * rs);
+  L.ui = take(9 * n * rs);
+  L.zv = take((size_t)(c.nx + 1) * (c.ny + 1) * rs);
+  L.man = take(n * rs);
+  L.bface = take((size_t)2 * (c.nx + c.ny) * sizeof(int));
+  L.segs = take(DG2_MAX_SEGMENTS * sizeof(Seg));
+  L.knots = take(2 * DG2_MAX_KNOTS * sizeof(double));
+  L.ctrl = take(sizeof(Ctrl));
+  L.ledger = take((size_t)L.n_tiles * 4 * sizeof(double));
+  L.scal = take(8 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+thread_local std::string g_init_err;
+
+}  // namespace
+
+struct dg2_ctx {
+  dg2_config cfg;
+  hipStream_t stream;
+  Layout L;
+  char* ws;
+  size_t n;
+  bool fp32;
+  bool has_manning;
+  double manning_scalar;
+  int nsegs;
+  int parity;          // state buffer holding the current U^n
+  Ctrl* h_ctrl;        // pinned mirror of the control block
+  double* h_scal;      // pinned totals
+  bool timing;
+  std::vector<hipEvent_t> ev;  // 3 events per timed step
+  size_t ev_used;
+  int64_t t_steps;
+  double t_ms1, t_ms2;
+  std::string err;
+};
+
+namespace {
+
+int fail(dg2_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPC(ctx, call)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return fail(ctx, DG2_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename R>
+Params<R> params(const dg2_ctx* c) {
+  Params<R> p{};
+  const Layout& L = c->L;
+  p.uin = reinterpret_cast<const R*>(c->ws + (c->parity ? L.u1 : L.u0));
+  p.vbuf = reinterpret_cast<R*>(c->ws + (c->parity ? L.u0 : L.u1));
+  p.ui = reinterpret_cast<R*>(c->ws + L.ui);
+  p.zv = reinterpret_cast<const R*>(c->ws + L.zv);
+  p.manning = c->has_manning ? reinterpret_cast<const R*>(c->ws + L.man) : nullptr;
+  p.bface = reinterpret_cast<const int*>(c->ws + L.bface);
+  p.segs = reinterpret_cast<const Seg*>(c->ws + L.segs);
+  p.knots = reinterpret_cast<const double*>(c->ws + L.knots);
+  p.ctrl = reinterpret_cast<Ctrl*>(c->ws + L.ctrl);
+  p.ledger = reinterpret_cast<double*>(c->ws + L.ledger);
+  p.n = (long long)c->n;
+  p.nx = c->cfg.nx;
+  p.ny = c->cfg.ny;
+  p.tiles_x = L.tiles_x;
+  p.n_tiles = L.n_tiles;
+  p.per_xcd = L.per_xcd;
+  p.nsegs = c->nsegs;
+  p.max_knots = DG2_MAX_KNOTS;
+  p.limiter = c->cfg.limiter;
+  p.parity = c->parity;
+  p.dx = R(c->cfg.dx);
+  p.g = R(c->cfg.g);
+  p.h_tol = R(c->cfg.h_tol);
+  p.n_scalar = R(c->manning_scalar);
+  p.dxd = c->cfg.dx;
+  p.gd = c->cfg.g;
+  p.cfl = c->cfg.cfl;
+  p.htd = c->cfg.h_tol;
+  p.dt_dry = c->cfg.dt_dry;
+  p.dt_max = 0.0;
+  p.t_end = INFINITY;
+  return p;
+}
+
+template <typename R>
+int launch_step(dg2_ctx* c, double dt_max, double t_end) {
+  Params<R> p = params<R>(c);
+  p.dt_max = dt_max;
+  p.t_end = t_end;
+  const dim3 grid(c->L.grid), block(dg2k::NT);
+  hipEvent_t* e = nullptr;
+  if (c->timing) {
+    if (c->ev_used + 3 > c->ev.size()) {
+      const size_t old = c->ev.size();
+      c->ev.resize(old + 3 * 1024);
+      for (size_t k = old; k < c->ev.size(); ++k) HIPC(c, hipEventCreate(&c->ev[k]));
+    }
+    e = &c->ev[c->ev_used];
+    c->ev_used += 3;
+    HIPC(c, hipEventRecord(e[0], c->stream));
+  }
+  hipLaunchKernelGGL((dg2k::stage_kernel<R, 1>), grid, block, 0, c->stream, p);
+  HIPC(c, hipGetLastError());
+  if (e) HIPC(c, hipEventRecord(e[1], c->stream));
+  hipLaunchKernelGGL((dg2k::stage_kernel<R, 2>), grid, block, 0, c->stream, p);
+  HIPC(c, hipGetLastError());
+  if (e) HIPC(c, hipEventRecord(e[2], c->stream));
+  c->parity ^= 1;
+  return DG2_OK;
+}
+
+int step_any(dg2_ctx* c, double dt_max, double t_end) {
+  return c->fp32 ? launch_step<float>(c, dt_max, t_end) : launch_step<double>(c, dt_max, t_end);
+}
+
+int pull_ctrl(dg2_ctx* c) {
+  HIPC(c, hipMemcpyAsync(c->h_ctrl, c->ws + c->L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost,
+                         c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return DG2_OK;
+}
+
+int check_health(dg2_ctx* c) {
+  const int h = c->h_ctrl->health;
+  if (h & 1) return fail(c, DG2_E_NUMERIC, "NaN in the state by step %lld", (long long)c->h_ctrl->step[c->parity]);
+  if (h & 2) return fail(c, DG2_E_NUMERIC, "CFL time step below 1e-12 s by step %lld", (long long)c->h_ctrl->step[c->parity]);
+  return DG2_OK;
+}
+
+template <typename R>
+int launch_dtc(dg2_ctx* c, double t) {
+  Params<R> p = params<R>(c);
+  const R* u = reinterpret_cast<const R*>(c->ws + (c->parity ? c->L.u1 : c->L.u0));
+  long long blocks = ((long long)c->n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL((dg2k::dtc_kernel<R>), dim3((unsigned)blocks), dim3(256), 0, c->stream, p, u, t,
+                     c->parity);
+  HIPC(c, hipGetLastError());
+  return DG2_OK;
+}
+
+bool finite_all(const double* a, size_t n) {
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(a[k])) return false;
+  return true;
+}
+
+int edge_len(const dg2_config& c, int edge) { return edge <= DG2_EDGE_E ? c.ny : c.nx; }
+
+int check_config(const dg2_config* cfg) {
+  if (!cfg) return fail(nullptr, DG2_E_ARG, "null config");
+  if (cfg->nx < 1 || cfg->ny < 1) return DG2_E_ARG;
+  if ((long long)cfg->nx * cfg->ny > (1LL << 31)) return DG2_E_UNSUPPORTED;
+  if (cfg->precision != DG2_FP64 && cfg->precision != DG2_FP32) return DG2_E_ARG;
+  return DG2_OK;
+}
+
+template <typename R>
+int init_device(dg2_ctx* c, const double* zv, const double* man, int mode, const double* data,
+                double eta) {
+  const size_t n = c->n, nv = (size_t)(c->cfg.nx + 1) * (c->cfg.ny + 1);
+  size_t staged = nv;
+  if (man) staged = std::max(staged, n);
+  if (mode == DG2_INIT_PLANES) staged = std::max(staged, 9 * n);
+  if (mode == DG2_INIT_MEANS) staged = std::max(staged, 3 * n);
+  if (mode == DG2_INIT_VERTEX) staged = std::max(staged, 3 * nv);
+  double* st = nullptr;
+  HIPC(c, hipMalloc(&st, staged * sizeof(double)));
+  int rc = DG2_OK;
+  auto conv = [&](const double* src, size_t cnt, size_t dst_off) -> int {
+    HIPC(c, hipMemcpyAsync(st, src, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const unsigned blocks = (unsigned)((cnt + 255) / 256);
+    hipLaunchKernelGGL((dg2k::convert_kernel<R>), dim3(blocks), dim3(256), 0, c->stream, st,
+                       reinterpret_cast<R*>(c->ws + dst_off), (long long)cnt);
+    HIPC(c, hipGetLastError());
+    HIPC(c, hipStreamSynchronize(c->stream));
+    return DG2_OK;
+  };
+  do {
+    if ((rc = conv(zv, nv, c->L.zv))) break;
+    if (man && (rc = conv(man, n, c->L.man))) break;
+    if (mode != DG2_INIT_LEVEL) {
+      size_t cnt = mode == DG2_INIT_PLANES ? 9 * n : (mode == DG2_INIT_MEANS ? 3 * n : 3 * nv);
+      hipError_t e = hipMemcpyAsync(st, data, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream);
+      if (e != hipSuccess) { rc = fail(c, DG2_E_DEVICE, "staging copy: %s", hipGetErrorString(e)); break; }
+    }
+    Params<R> p = params<R>(c);
+    p.vbuf = reinterpret_cast<R*>(c->ws + c->L.u0);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL((dg2k::init_kernel<R>), dim3(blocks), dim3(256), 0, c->stream, p, st, mode, eta);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { rc = fail(c, DG2_E_DEVICE, "init kernel: %s", hipGetErrorString(e)); break; }
+  } while (false);
+  (void)hipFree(st);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg2_workspace_size(const dg2_config* cfg, size_t* bytes) {
+  if (!bytes) return DG2_E_ARG;
+  const int rc = check_config(cfg);
+  if (rc) return rc;
+  *bytes = layout(*cfg).total;
+  return DG2_OK;
+}
+
+const char* dg2_init_error(void) { return g_init_err.c_str(); }
+
+int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, double manning_scalar,
+             int32_t init_mode, const double* init_data, double eta_level, const dg2_boundary* bcs,
+             int32_t n_bcs, void* d_workspace, size_t ws_bytes, void* hip_stream, dg2_ctx** out) {
+  g_init_err.clear();
+  auto bad = [](int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_init_err = buf;
+    return code;
+  };
+  if (!out) return bad(DG2_E_ARG, "null output pointer");
+  *out = nullptr;
+  int rc = check_config(cfg);
+  if (rc) return bad(rc, "bad grid size or precision");
+  const dg2_config& c = *cfg;
+  if (!(c.dx > 0) || !(c.g > 0) || !(c.cfl > 0) || !(c.h_tol >= 0) || !(c.dt_dry > 0) ||
+      !std::isfinite(c.t0) || !std::isfinite(c.dx) || !std::isfinite(c.g))
+    return bad(DG2_E_ARG, "bad scalar parameter");
+  for (int e = 0; e < 4; ++e)
+    if (c.edge_kind[e] != DG2_BC_TRANSMISSIVE && c.edge_kind[e] != DG2_BC_WALL)
+      return bad(DG2_E_ARG, "edge default must be transmissive or wall");
+  if (!zv) return bad(DG2_E_ARG, "null bed");
+  const size_t n = (size_t)c.nx * c.ny, nv = (size_t)(c.nx + 1) * (c.ny + 1);
+  if (!finite_all(zv, nv)) return bad(DG2_E_ARG, "non-finite bed elevation");
+  if (manning) {
+    for (size_t k = 0; k < n; ++k)
+      if (!(manning[k] >= 0) || !std::isfinite(manning[k])) return bad(DG2_E_ARG, "bad Manning n at cell %zu", k);
+  } else if (!(manning_scalar >= 0) || !std::isfinite(manning_scalar)) {
+    return bad(DG2_E_ARG, "bad Manning n");
+  }
+  if (init_mode == DG2_INIT_PLANES || init_mode == DG2_INIT_MEANS) {
+    const size_t cnt = (init_mode == DG2_INIT_PLANES ? 9 : 3) * n;
+    if (!init_data || !finite_all(init_data, cnt)) return bad(DG2_E_ARG, "bad initial data");
+    for (size_t k = 0; k < n; ++k)
+      if (init_data[k] < 0) return bad(DG2_E_ARG, "negative mean depth at cell %zu", k);
+  } else if (init_mode == DG2_INIT_VERTEX) {
+    if (!init_data || !finite_all(init_data, 3 * nv)) return bad(DG2_E_ARG, "bad initial vertex data");
+    for (size_t k = 0; k < nv; ++k)
+      if (init_data[k] < 0) return bad(DG2_E_ARG, "negative vertex depth");
+  } else if (init_mode == DG2_INIT_LEVEL) {
+    if (!std::isfinite(eta_level)) return bad(DG2_E_ARG, "bad still-water level");
+  } else {
+    return bad(DG2_E_ARG, "bad init mode %d", init_mode);
+  }
+  // boundary table
+  if (n_bcs < 0 || n_bcs > DG2_MAX_SEGMENTS || (n_bcs > 0 && !bcs)) return bad(DG2_E_ARG, "bad boundary list");
+  std::vector<int> bface(2 * (size_t)(c.nx + c.ny));
+  const size_t eoff[4] = {0, (size_t)c.ny, 2 * (size_t)c.ny, 2 * (size_t)c.ny + c.nx};
+  for (int e = 0; e < 4; ++e)
+    for (int f = 0; f < edge_len(c, e); ++f) bface[eoff[e] + f] = c.edge_kind[e];
+  std::vector<Seg> segs(DG2_MAX_SEGMENTS);
+  std::vector<double> knots(2 * DG2_MAX_KNOTS, 0.0);
+  std::vector<char> covered(bface.size(), 0);
+  int kused = 0;
+  for (int s = 0; s < n_bcs; ++s) {
+    const dg2_boundary& b = bcs[s];
+    if (b.edge < 0 || b.edge > 3) return bad(DG2_E_ARG, "boundary %d: bad edge", s);
+    if (b.kind < 0 || b.kind > 3) return bad(DG2_E_ARG, "boundary %d: bad kind", s);
+    if (b.i0 < 0 || b.i1 > edge_len(c, b.edge) || b.i0 >= b.i1) return bad(DG2_E_ARG, "boundary %d: bad range", s);
+    Seg& g = segs[s];
+    g.kind = b.kind; g.edge = b.edge; g.i0 = b.i0; g.i1 = b.i1; g.k0 = 0; g.nk = 0;
+    g.width = (double)(b.i1 - b.i0) * c.dx;
+    g.h_b = b.h_b; g.u_b = b.u_b; g.v_b = b.v_b;
+    if (b.kind == DG2_BC_FIXED && (!(b.h_b >= 0) || !std::isfinite(b.h_b) || !std::isfinite(b.u_b) || !std::isfinite(b.v_b)))
+      return bad(DG2_E_ARG, "boundary %d: bad fixed state", s);
+    if (b.kind == DG2_BC_INFLOW) {
+      if (b.n_knots < 1 || !b.t_knots || !b.q_knots) return bad(DG2_E_ARG, "boundary %d: no hydrograph", s);
+      if (kused + b.n_knots > DG2_MAX_KNOTS) return bad(DG2_E_ARG, "too many hydrograph knots");
+      for (int k = 0; k < b.n_knots; ++k) {
+        if (!std::isfinite(b.t_knots[k]) || !std::isfinite(b.q_knots[k]) || b.q_knots[k] < 0)
+          return bad(DG2_E_ARG, "boundary %d: bad knot %d", s, k);
+        if (k > 0 && !(b.t_knots[k] > b.t_knots[k - 1])) return bad(DG2_E_ARG, "boundary %d: knots not increasing", s);
+        knots[kused + k] = b.t_knots[k];
+        knots[DG2_MAX_KNOTS + kused + k] = b.q_knots[k];
+      }
+      g.k0 = kused;
+      g.nk = b.n_knots;
+      kused += b.n_knots;
+    }
+    for (int f = b.i0; f < b.i1; ++f) {
+      if (covered[eoff[b.edge] + f]) return bad(DG2_E_ARG, "boundary %d overlaps another", s);
+      covered[eoff[b.edge] + f] = 1;
+      bface[eoff[b.edge] + f] = b.kind | ((s + 1) << 8);
+    }
+  }
+  const Layout L = layout(c);
+  if (!d_workspace || ws_bytes < L.total) return bad(DG2_E_ARG, "workspace needs %zu bytes", L.total);
+  if (reinterpret_cast<uintptr_t>(d_workspace) % ALIGN) return bad(DG2_E_ARG, "workspace not 256-byte aligned");
+
+  dg2_ctx* x = new (std::nothrow) dg2_ctx();
+  if (!x) return bad(DG2_E_ARG, "out of host memory");
+  x->cfg = c;
+  x->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  x->L = L;
+  x->ws = reinterpret_cast<char*>(d_workspace);
+  x->n = n;
+  x->fp32 = c.precision == DG2_FP32;
+  x->has_manning = manning != nullptr;
+  x->manning_scalar = manning_scalar;
+  x->nsegs = n_bcs;
+  x->parity = 0;
+  x->timing = false;
+  x->ev_used = 0;
+  x->t_steps = 0;
+  x->t_ms1 = x->t_ms2 = 0;
+  auto dev = [&](hipError_t e, const char* what) {
+    if (e == hipSuccess) return false;
+    g_init_err = std::string(what) + ": " + hipGetErrorString(e);
+    return true;
+  };
+  bool err = dev(hipHostMalloc((void**)&x->h_ctrl, sizeof(Ctrl)), "pinned control block") ||
+             dev(hipHostMalloc((void**)&x->h_scal, 8 * sizeof(double)), "pinned totals");
+  if (!err) {
+    Ctrl ctrl{};
+    ctrl.t[0] = ctrl.t[1] = c.t0;
+    ctrl.dtc[0] = ctrl.dtc[1] = dg2k::INF_BITS;
+    err = dev(hipMemcpyAsync(x->ws + L.ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice, x->stream), "control block") ||
+          dev(hipMemsetAsync(x->ws + L.ledger, 0, (size_t)L.n_tiles * 4 * sizeof(double), x->stream), "ledger") ||
+          dev(hipMemcpyAsync(x->ws + L.bface, bface.data(), bface.size() * sizeof(int), hipMemcpyHostToDevice, x->stream), "boundary faces") ||
+          dev(hipMemcpyAsync(x->ws + L.segs, segs.data(), segs.size() * sizeof(Seg), hipMemcpyHostToDevice, x->stream), "segments") ||
+          dev(hipMemcpyAsync(x->ws + L.knots, knots.data(), knots.size() * sizeof(double), hipMemcpyHostToDevice, x->stream), "knots") ||
+          dev(hipStreamSynchronize(x->stream), "set-up copies");
+  }
+  if (!err) {
+    rc = x->fp32 ? init_device<float>(x, zv, manning, init_mode, init_data, eta_level)
+                 : init_device<double>(x, zv, manning, init_mode, init_data, eta_level);
+    if (rc) { g_init_err = x->err; err = true; }
+  }
+  if (!err) {
+    rc = x->fp32 ? launch_dtc<float>(x, c.t0) : launch_dtc<double>(x, c.t0);
+    if (rc || pull_ctrl(x)) { g_init_err = x->err; err = true; }
+  }
+  if (err) {
+    dg2_destroy(x);
+    return DG2_E_DEVICE;
+  }
+  *out = x;
+  return DG2_OK;
+}
+
+int dg2_step(dg2_ctx* c, double dt_max, double* dt_used) {
+  if (!c) return DG2_E_ARG;
+  const int p = c->parity;
+  int rc = step_any(c, dt_max, INFINITY);
+  if (rc) return rc;
+  if (dt_used) {
+    if ((rc = pull_ctrl(c))) return rc;
+    *dt_used = c->h_ctrl->dt_used[p];
+    return check_health(c);
+  }
+  return DG2_OK;
+}
+
+int dg2_run(dg2_ctx* c, double t_end, int64_t* steps_taken) {
+  if (!c) return DG2_E_ARG;
+  int rc = pull_ctrl(c);
+  if (rc) return rc;
+  const double t_start = c->h_ctrl->t[c->parity];
+  const long long s_start = c->h_ctrl->step[c->parity];
+  if (!(t_end >= t_start)) return fail(c, DG2_E_ARG, "t_end %g is before t %g", t_end, t_start);
+  long long batch = 1;
+  while (true) {
+    const Ctrl& h = *c->h_ctrl;
+    const double t = h.t[c->parity];
+    if (steps_taken) *steps_taken = h.step[c->parity] - s_start;
+    if ((rc = check_health(c))) return rc;
+    if (t >= t_end) return DG2_OK;
+    // size the next batch from the current time step; steps issued past t_end are
+    // no-ops that only carry the state over
+    const double m = __builtin_bit_cast(double, h.dtc[c->parity]);
+    double dt = std::isinf(m) ? c->cfg.dt_dry : c->cfg.cfl * m;
+    double est = (t_end - t) / dt;
+    batch = est < 1 ? 1 : (long long)std::ceil(est);
+    if (batch > 256) batch = 256;
+    for (long long k = 0; k < batch; ++k)
+      if ((rc = step_any(c, 0.0, t_end))) return rc;
+    if ((rc = pull_ctrl(c))) return rc;
+  }
+}
+
+int dg2_read(dg2_ctx* c, int32_t field, void* dst, int32_t dst_is_device) {
+  if (!c || !dst || field < 0 || field > 11) return fail(c, DG2_E_ARG, "bad field or destination");
+  const size_t rs = c->fp32 ? 4 : 8;
+  const char* cur = c->ws + (c->parity ? c->L.u1 : c->L.u0);
+  const char* src = cur + (size_t)(field < 9 ? field : 0) * c->n * rs;
+  if (field >= 9) {
+    char* tmp = c->ws + c->L.ui;  // stage scratch, free between steps
+    const unsigned blocks = (unsigned)((c->n + 255) / 256);
+    if (c->fp32) {
+      Params<float> p = params<float>(c);
+      hipLaunchKernelGGL((dg2k::field_kernel<float>), dim3(blocks), dim3(256), 0, c->stream, p,
+                         reinterpret_cast<const float*>(cur), field, reinterpret_cast<float*>(tmp));
+    } else {
+      Params<double> p = params<double>(c);
+      hipLaunchKernelGGL((dg2k::field_kernel<double>), dim3(blocks), dim3(256), 0, c->stream, p,
+                         reinterpret_cast<const double*>(cur), field, reinterpret_cast<double*>(tmp));
+    }
+    HIPC(c, hipGetLastError());
+    src = tmp;
+  }
+  HIPC(c, hipMemcpyAsync(dst, src, c->n * rs, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return DG2_OK;
+}
+
+int dg2_get_scalars(dg2_ctx* c, double* t, int64_t* step, double* mass, double* mass_in, double* mass_out,
+                    double* mass_clip) {
+  if (!c) return DG2_E_ARG;
+  const char* cur = c->ws + (c->parity ? c->L.u1 : c->L.u0);
+  double* dout = reinterpret_cast<double*>(c->ws + c->L.scal);
+  const double area = c->cfg.dx * c->cfg.dx;
+  const double* led = reinterpret_cast<const double*>(c->ws + c->L.ledger);
+  if (c->fp32)
+    hipLaunchKernelGGL((dg2k::totals_kernel<float>), dim3(1), dim3(1024), 0, c->stream,
+                       reinterpret_cast<const float*>(cur), (long long)c->n, led, c->L.n_tiles, area, dout);
+  else
+    hipLaunchKernelGGL((dg2k::totals_kernel<double>), dim3(1), dim3(1024), 0, c->stream,
+                       reinterpret_cast<const double*>(cur), (long long)c->n, led, c->L.n_tiles, area, dout);
+  HIPC(c, hipGetLastError());
+  HIPC(c, hipMemcpyAsync(c->h_scal, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  int rc = pull_ctrl(c);
+  if (rc) return rc;
+  if (t) *t = c->h_ctrl->t[c->parity];
+  if (step) *step = c->h_ctrl->step[c->parity];
+  if (mass) *mass = c->h_scal[0];
+  if (mass_in) *mass_in = c->h_scal[1];
+  if (mass_out) *mass_out = c->h_scal[2];
+  if (mass_clip) *mass_clip = c->h_scal[3];
+  return DG2_OK;
+}
+
+int dg2_next_dt(dg2_ctx* c, double* dt) {
+  if (!c || !dt) return DG2_E_ARG;
+  const int rc = pull_ctrl(c);
+  if (rc) return rc;
+  const double m = __builtin_bit_cast(double, c->h_ctrl->dtc[c->parity]);
+  *dt = std::isinf(m) ? c->cfg.dt_dry : c->cfg.cfl * m;
+  return DG2_OK;
+}
+
+// blob: header (8 x int64), t, step, dtc bits, ledger (n_tiles x 4 doubles), planes
+namespace {
+constexpr int64_t MAGIC = 0x4447325354415445LL;  // "DG2STATE"
+size_t blob_bytes(const dg2_ctx* c) {
+  return 8 * 8 + 3 * 8 + (size_t)c->L.n_tiles * 4 * 8 + 9 * c->n * (c->fp32 ? 4 : 8);
+}
+}  // namespace
+
+int dg2_state_bytes(const dg2_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return DG2_E_ARG;
+  *bytes = blob_bytes(c);
+  return DG2_OK;
+}
+
+int dg2_get_state(dg2_ctx* c, void* host_dst) {
+  if (!c || !host_dst) return DG2_E_ARG;
+  int rc = pull_ctrl(c);
+  if (rc) return rc;
+  char* b = reinterpret_cast<char*>(host_dst);
+  int64_t hdr[8] = {MAGIC, c->fp32 ? 1 : 0, c->cfg.nx, c->cfg.ny, c->L.n_tiles, dg2k::TX, dg2k::TY, 0};
+  std::memcpy(b, hdr, sizeof hdr);
+  double* s = reinterpret_cast<double*>(b + sizeof hdr);
+  s[0] = c->h_ctrl->t[c->parity];
+  s[1] = (double)c->h_ctrl->step[c->parity];
+  std::memcpy(&s[2], &c->h_ctrl->dtc[c->parity], 8);
+  char* led = b + sizeof hdr + 24;
+  HIPC(c, hipMemcpyAsync(led, c->ws + c->L.ledger, (size_t)c->L.n_tiles * 32, hipMemcpyDeviceToHost, c->stream));
+  char* pl = led + (size_t)c->L.n_tiles * 32;
+  HIPC(c, hipMemcpyAsync(pl, c->ws + (c->parity ? c->L.u1 : c->L.u0), 9 * c->n * (c->fp32 ? 4 : 8),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return DG2_OK;
+}
+
+int dg2_set_state(dg2_ctx* c, const void* host_src) {
+  if (!c || !host_src) return DG2_E_ARG;
+  const char* b = reinterpret_cast<const char*>(host_src);
+  int64_t hdr[8];
+  std::memcpy(hdr, b, sizeof hdr);
+  if (hdr[0] != MAGIC || hdr[1] != (c->fp32 ? 1 : 0) || hdr[2] != c->cfg.nx || hdr[3] != c->cfg.ny ||
+      hdr[4] != c->L.n_tiles || hdr[5] != dg2k::TX || hdr[6] != dg2k::TY)
+    return fail(c, DG2_E_STATE, "state blob does not match this context");
+  int rc = pull_ctrl(c);
+  if (rc) return rc;
+  const double* s = reinterpret_cast<const double*>(b + sizeof hdr);
+  Ctrl ctrl = *c->h_ctrl;
+  ctrl.t[c->parity] = s[0];
+  ctrl.step[c->parity] = (long long)s[1];
+  std::memcpy(&ctrl.dtc[c->parity], &s[2], 8);
+  ctrl.health = 0;
+  HIPC(c, hipMemcpyAsync(c->ws + c->L.ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice, c->stream));
+  const char* led = b + sizeof hdr + 24;
+  HIPC(c, hipMemcpyAsync(c->ws + c->L.ledger, led, (size_t)c->L.n_tiles * 32, hipMemcpyHostToDevice, c->stream));
+  const char* pl = led + (size_t)c->L.n_tiles * 32;
+  HIPC(c, hipMemcpyAsync(c->ws + (c->parity ? c->L.u1 : c->L.u0), pl, 9 * c->n * (c->fp32 ? 4 : 8),
+                         hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return DG2_OK;
+}
+
+int dg2_set_timing(dg2_ctx* c, int32_t on) {
+  if (!c) return DG2_E_ARG;
+  HIPC(c, hipStreamSynchronize(c->stream));
+  c->timing = on != 0;
+  c->ev_used = 0;
+  c->t_steps = 0;
+  c->t_ms1 = c->t_ms2 = 0;
+  return DG2_OK;
+}
+
+int dg2_get_timing(dg2_ctx* c, int64_t* steps, double* ms1, double* ms2) {
+  if (!c) return DG2_E_ARG;
+  HIPC(c, hipStreamSynchronize(c->stream));
+  for (size_t k = 0; k + 3 <= c->ev_used; k += 3) {
+    float a = 0, b = 0;
+    HIPC(c, hipEventElapsedTime(&a, c->ev[k], c->ev[k + 1]));
+    HIPC(c, hipEventElapsedTime(&b, c->ev[k + 1], c->ev[k + 2]));
+    c->t_ms1 += a;
+    c->t_ms2 += b;
+    c->t_steps += 1;
+  }
+  c->ev_used = 0;
+  if (steps) *steps = c->t_steps;
+  if (ms1) *ms1 = c->t_steps ? c->t_ms1 / c->t_steps : 0.0;
+  if (ms2) *ms2 = c->t_steps ? c->t_ms2 / c->t_steps : 0.0;
+  return DG2_OK;
+}
+
+int dg2_kernel_info(const dg2_ctx* c, int32_t* tile_x, int32_t* tile_y, int32_t* threads, int32_t* blocks,
+                    int32_t* lds_bytes) {
+  if (!c) return DG2_E_ARG;
+  const int rs = c->fp32 ? 4 : 8;
+  if (tile_x) *tile_x = dg2k::TX;
+  if (tile_y) *tile_y = dg2k::TY;
+  if (threads) *threads = dg2k::NT;
+  if (blocks) *blocks = c->L.grid;
+  if (lds_bytes) *lds_bytes = 12 * dg2k::RB * rs + dg2k::RB + (dg2k::NT / 64) * 4 * 8;
+  return DG2_OK;
+}
+
+const char* dg2_last_error(const dg2_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void dg2_destroy(dg2_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+  if (c->h_scal) (void)hipHostFree(c->h_scal);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+"""Thin ctypes binding of the gfx950 DG2 library (libdg2.so, interface in include/dg2.h).
+
+Argument marshalling only: every step of the method runs in the library's kernels.
+PyTorch provides the device workspace (a uint8 tensor) and the HIP stream (torch's
+current stream at construction). If the library has not been built, loading fails with
+an error; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdg2.so")
+
+FP64, FP32 = 0, 1
+OK, E_ARG, E_DEVICE, E_NUMERIC, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+MAX_SEGMENTS, MAX_KNOTS = 64, 8192
+SYMBOLS = ("dg2_workspace_size", "dg2_init", "dg2_step", "dg2_run", "dg2_read",
+           "dg2_get_scalars", "dg2_next_dt", "dg2_state_bytes", "dg2_get_state",
+           "dg2_set_state", "dg2_set_timing", "dg2_get_timing", "dg2_kernel_info",
+           "dg2_last_error", "dg2_init_error", "dg2_destroy")
+
+_dp = C.POINTER(C.c_double)
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("g", C.c_double),
+                ("cfl", C.c_double), ("h_tol", C.c_double), ("dt_dry", C.c_double),
+                ("t0", C.c_double), ("precision", C.c_int32), ("limiter", C.c_int32),
+                ("edge_kind", C.c_int32 * 4)]
+
+
+class Boundary(C.Structure):
+    _fields_ = [("edge", C.c_int32), ("kind", C.c_int32), ("i0", C.c_int32), ("i1", C.c_int32),
+                ("n_knots", C.c_int32), ("t_knots", _dp), ("q_knots", _dp),
+                ("h_b", C.c_double), ("u_b", C.c_double), ("v_b", C.c_double)]
+
+
+class DG2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dg2 error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdg2.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = C.CDLL(path)
+    vp, sz = C.c_void_p, C.c_size_t
+    i32, i64 = C.c_int32, C.c_int64
+    lib.dg2_workspace_size.argtypes = [C.POINTER(Config), C.POINTER(sz)]
+    lib.dg2_init.argtypes = [C.POINTER(Config), _dp, _dp, C.c_double, i32, _dp, C.c_double,
+                             C.POINTER(Boundary), i32, vp, sz, vp, C.POINTER(vp)]
+    lib.dg2_step.argtypes = [vp, C.c_double, _dp]
+    lib.dg2_run.argtypes = [vp, C.c_double, C.POINTER(i64)]
+    lib.dg2_read.argtypes = [vp, i32, vp, i32]
+    lib.dg2_get_scalars.argtypes = [vp, _dp, C.POINTER(i64), _dp, _dp, _dp, _dp]
+    lib.dg2_next_dt.argtypes = [vp, _dp]
+    lib.dg2_state_bytes.argtypes = [vp, C.POINTER(sz)]
+    lib.dg2_get_state.argtypes = [vp, vp]
+    lib.dg2_set_state.argtypes = [vp, vp]
+    lib.dg2_set_timing.argtypes = [vp, i32]
+    lib.dg2_get_timing.argtypes = [vp, C.POINTER(i64), _dp, _dp]
+    lib.dg2_kernel_info.argtypes = [vp] + [C.POINTER(i32)] * 5
+    lib.dg2_last_error.argtypes = [vp]
+    lib.dg2_last_error.restype = C.c_char_p
+    lib.dg2_init_error.argtypes = []
+    lib.dg2_init_error.restype = C.c_char_p
+    lib.dg2_destroy.argtypes = [vp]
+    lib.dg2_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def make_config(sc, precision: int) -> Config:
+    return Config(int(sc.nx), int(sc.ny), float(sc.dx), float(sc.g), float(sc.cfl),
+                  float(sc.h_tol), float(sc.dt_dry), float(sc.t0), int(precision),
+                  int(sc.limiter), (C.c_int32 * 4)(*[int(k) for k in sc.edge_kind]))
+
+
+def workspace_bytes(sc, precision: int = FP64) -> int:
+    lib = load()
+    cfg = make_config(sc, precision)
+    out = C.c_size_t()
+    rc = lib.dg2_workspace_size(C.byref(cfg), C.byref(out))
+    if rc != 0:
+        raise DG2Error(rc, "workspace size")
+    return out.value
+
+
+class DG2:
+    """One simulation on the GPU, built from a scenario (see the seeded generators):
+    attributes nx, ny, dx, g, cfl, h_tol, dt_dry, t0, limiter, edge_kind, zv, manning,
+    manning_scalar, init_mode, init_data, eta_level, boundaries."""
+
+    PLANES = ("h0", "h1x", "h1y", "qx0", "qx1x", "qx1y", "qy0", "qy1x", "qy1y")
+
+    def __init__(self, sc, precision: int = FP64, device: str = "cuda:0", stream=None):
+        import torch
+        lib = load()
+        self._lib = lib
+        self.nx, self.ny = int(sc.nx), int(sc.ny)
+        self.precision = precision
+        self.dtype = np.float32 if precision == FP32 else np.float64
+        self.torch_dtype = torch.float32 if precision == FP32 else torch.float64
+        self.device = torch.device(device)
+        cfg = make_config(sc, precision)
+        ws = C.c_size_t()
+        rc = lib.dg2_workspace_size(C.byref(cfg), C.byref(ws))
+        if rc != 0:
+            raise DG2Error(rc, "bad configuration")
+        self.workspace = torch.empty(ws.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        keep = []
+        zv, man, data = _f64(sc.zv), _f64(sc.manning), _f64(sc.init_data)
+        keep += [zv, man, data]
+        nb = len(sc.boundaries)
+        arr = (Boundary * max(nb, 1))()
+        for k, b in enumerate(sc.boundaries):
+            tk, qk = _f64(b.t_knots), _f64(b.q_knots)
+            keep += [tk, qk]
+            arr[k] = Boundary(b.edge, b.kind, b.i0, b.i1, 0 if tk is None else len(tk),
+                              _ptr(tk), _ptr(qk), b.h_b, b.u_b, b.v_b)
+        h = C.c_void_p()
+        rc = lib.dg2_init(C.byref(cfg), _ptr(zv), _ptr(man), float(sc.manning_scalar),
+                          int(sc.init_mode), _ptr(data), float(sc.eta_level), arr, nb,
+                          C.c_void_p(self.workspace.data_ptr()), ws.value,
+                          C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise DG2Error(rc, lib.dg2_init_error().decode())
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.dg2_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc != 0:
+            raise DG2Error(rc, self._lib.dg2_last_error(self._h).decode())
+
+    def step(self, dt_max: float = 0.0, sync: bool = True):
+        """One RK2 step; returns the dt taken if sync, else None (nothing waits)."""
+        if sync:
+            dt = C.c_double()
+            self._check(self._lib.dg2_step(self._h, dt_max, C.byref(dt)))
+            return dt.value
+        self._check(self._lib.dg2_step(self._h, dt_max, None))
+        return None
+
+    def run(self, t_end: float) -> int:
+        k = C.c_int64()
+        self._check(self._lib.dg2_run(self._h, t_end, C.byref(k)))
+        return k.value
+
+    def read(self, field: int) -> np.ndarray:
+        out = np.empty((self.ny, self.nx), dtype=self.dtype)
+        self._check(self._lib.dg2_read(self._h, field, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def read_device(self, field: int):
+        import torch
+        out = torch.empty((self.ny, self.nx), dtype=self.torch_dtype, device=self.device)
+        self._check(self._lib.dg2_read(self._h, field, C.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def planes(self) -> np.ndarray:
+        return np.stack([self.read(p) for p in range(9)])
+
+    def scalars(self) -> dict:
+        t, m, mi, mo, mc = (C.c_double() for _ in range(5))
+        st = C.c_int64()
+        self._check(self._lib.dg2_get_scalars(self._h, C.byref(t), C.byref(st), C.byref(m),
+                                              C.byref(mi), C.byref(mo), C.byref(mc)))
+        return dict(t=t.value, step=st.value, mass=m.value, mass_in=mi.value,
+                    mass_out=mo.value, mass_clip=mc.value)
+
+    def next_dt(self) -> float:
+        d = C.c_double()
+        self._check(self._lib.dg2_next_dt(self._h, C.byref(d)))
+        return d.value
+
+    def get_state(self) -> bytes:
+        n = C.c_size_t()
+        self._check(self._lib.dg2_state_bytes(self._h, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(self._lib.dg2_get_state(self._h, buf))
+        return buf.raw
+
+    def set_state(self, blob: bytes) -> None:
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(self._lib.dg2_set_state(self._h, buf))
+
+    def set_timing(self, on: bool) -> None:
+        self._check(self._lib.dg2_set_timing(self._h, int(on)))
+
+    def timing(self) -> dict:
+        s = C.c_int64()
+        a, b = C.c_double(), C.c_double()
+        self._check(self._lib.dg2_get_timing(self._h, C.byref(s), C.byref(a), C.byref(b)))
+        return dict(steps=s.value, ms_stage1=a.value, ms_stage2=b.value)
+
+    def kernel_info(self) -> dict:
+        v = [C.c_int32() for _ in range(5)]
+        self._check(self._lib.dg2_kernel_info(self._h, *[C.byref(x) for x in v]))
+        return dict(zip(("tile_x", "tile_y", "threads", "blocks", "lds_bytes"),
+                        [x.value for x in v]))

@@ -172,9 +172,9 @@ def trapezoid_hydrograph(q_peak: float, t_rise: float, t_hold_end: float,
 
 def fbm_channel(n: int = 1024, dx: float = 5.0, seed: int = 2, hurst: float = 0.8,
                 relief: float = 20.0, channel_width: float = 30.0,
-                channel_depth: float = 3.0, amplitude: float = 500.0,
-                wavelength: float = 2000.0, q_peak: float = 50.0, manning: float = 0.035,
-                t_end: float = 7200.0) -> Scenario:
+                channel_depth: float = 3.0, amplitude: Optional[float] = None,
+                wavelength: Optional[float] = None, q_peak: float = 50.0,
+                manning: float = 0.035, t_end: float = 7200.0) -> Scenario:
     """Rugged terrain with a carved meandering channel, initially dry, fed at the west
     edge by a trapezoid hydrograph (0 -> q_peak over 900 s, held to 2700 s, back to 0
     at 3600 s); the other edges are transmissive.
@@ -182,7 +182,13 @@ def fbm_channel(n: int = 1024, dx: float = 5.0, seed: int = 2, hurst: float = 0.
     The channel centreline is y_c(x) = L/2 + amplitude sin(2 pi x / wavelength + phi);
     vertices within half the channel width of it are lowered to the running minimum
     (from the west) of the terrain along the centreline minus channel_depth, so the
-    channel bed never rises downstream."""
+    channel bed never rises downstream. By default the meander has amplitude 500 m and
+    wavelength 2000 m on the 1024-cell, 5 m grid, and both scale with the domain length
+    otherwise."""
+    if amplitude is None:
+        amplitude = 500.0 * n * dx / 5120.0
+    if wavelength is None:
+        wavelength = 2000.0 * n * dx / 5120.0
     rng = np.random.default_rng(seed + 1000)
     zv = fbm_vertices(n + 1, seed, hurst, relief)
     phi = rng.uniform(0.0, 2.0 * np.pi)
@@ -264,3 +270,15 @@ def window(sc: Scenario, nx: int, ny: int, i0: int = 0, j0: int = 0) -> Scenario
             bcs.append(dataclasses.replace(b, i0=lo, i1=hi))
     return dataclasses.replace(sc, name=sc.name + f"_win{nx}x{ny}", nx=nx, ny=ny, zv=zv,
                                init_data=data, manning=man, boundaries=bcs)
+
+
+def urban_wet(n: int = 2048, dx: float = 2.0, seed: int = 3, n_blocks: int = 4000,
+              eta: float = 2.0, qx: float = 1.0, manning: float = 0.02) -> Scenario:
+    """The urban_blocks terrain under water to level eta between the blocks (vertex
+    depth eta - z where positive) with an eastward discharge qx where wet: flow around
+    every block, wet/dry fronts at every block wall."""
+    base = urban_blocks(n, dx, seed, n_blocks, manning=manning)
+    depth = np.maximum(eta - base.zv, 0.0)
+    vert = np.stack([depth, np.where(depth > 0, qx, 0.0), np.zeros_like(depth)])
+    return Scenario("urban_wet", n, n, dx, base.zv, MODE_VERTEX, vert,
+                    manning_scalar=manning, boundaries=base.boundaries, t_end=60.0)
