@@ -36,6 +36,33 @@ def stage_bytes(n_cells, real_bytes):
     return VALUES_PER_CELL_LAUNCH * real_bytes * n_cells
 
 
+def kernel_source_hash():
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2107_02750_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, precision_tag, n):
+    """HBM bytes per launch of a stage kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None
+    when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles",
+                        f"traffic_stage_kernels_fbm_channel_wet_{n}_{precision_tag}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    k = rec["kib_per_dispatch"][kernel]
+    sc = rec["copy_scale"]
+    return 1024.0 * (k["fetch"] * sc["fetch"] + k["write"] * sc["write"])
+
+
 def timed_steps(sim, steps):
     import torch
     sim.set_timing(True)
@@ -133,7 +160,8 @@ def main():
                    "blocks_per_launch": info["blocks"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "ms_per_launch": {"stage1": ms1, "stage2": ms2},
+                     "traffic": measured_traffic(dom, "fp64", args.n),
+                     "ms_per_launch": {"stage1": ms1, "stage2": ms2},
                      "algorithmic_bytes_per_launch": stage_bytes(n_cells, 8)},
     }
     if not args.no_extras:
