@@ -25,15 +25,18 @@ size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t u0, u1, ui, zv, man, bface, segs, knots, ctrl, ledger, scal, total;
-  int tiles_x, tiles_y, n_tiles, per_xcd, grid;
+  int tx, ty, threads, tiles_x, tiles_y, n_tiles, per_xcd, grid;
 };
 
 Layout layout(const dg2_config& c) {
   Layout L{};
   const size_t n = (size_t)c.nx * c.ny;
   const size_t rs = c.precision == DG2_FP32 ? 4 : 8;
-  L.tiles_x = (c.nx + dg2k::TX - 1) / dg2k::TX;
-  L.tiles_y = (c.ny + dg2k::TY - 1) / dg2k::TY;
+  L.tx = c.precision == DG2_FP32 ? dg2k::Geo<float>::TX : dg2k::Geo<double>::TX;
+  L.ty = c.precision == DG2_FP32 ? dg2k::Geo<float>::TY : dg2k::Geo<double>::TY;
+  L.threads = L.tx * L.ty;
+  L.tiles_x = (c.nx + L.tx - 1) / L.tx;
+  L.tiles_y = (c.ny + L.ty - 1) / L.ty;
   L.n_tiles = L.tiles_x * L.tiles_y;
   L.per_xcd = (L.n_tiles + dg2k::NXCD - 1) / dg2k::NXCD;
   L.grid = L.per_xcd * dg2k::NXCD;
@@ -144,7 +147,7 @@ int launch_step(dg2_ctx* c, double dt_max, double t_end) {
   Params<R> p = params<R>(c);
   p.dt_max = dt_max;
   p.t_end = t_end;
-  const dim3 grid(c->L.grid), block(dg2k::NT);
+  const dim3 grid(c->L.grid), block(c->L.threads);
   hipEvent_t* e = nullptr;
   if (c->timing) {
     if (c->ev_used + 3 > c->ev.size()) {
@@ -530,7 +533,7 @@ int dg2_get_state(dg2_ctx* c, void* host_dst) {
   int rc = pull_ctrl(c);
   if (rc) return rc;
   char* b = reinterpret_cast<char*>(host_dst);
-  int64_t hdr[8] = {MAGIC, c->fp32 ? 1 : 0, c->cfg.nx, c->cfg.ny, c->L.n_tiles, dg2k::TX, dg2k::TY, 0};
+  int64_t hdr[8] = {MAGIC, c->fp32 ? 1 : 0, c->cfg.nx, c->cfg.ny, c->L.n_tiles, c->L.tx, c->L.ty, 0};
   std::memcpy(b, hdr, sizeof hdr);
   double* s = reinterpret_cast<double*>(b + sizeof hdr);
   s[0] = c->h_ctrl->t[c->parity];
@@ -551,7 +554,7 @@ int dg2_set_state(dg2_ctx* c, const void* host_src) {
   int64_t hdr[8];
   std::memcpy(hdr, b, sizeof hdr);
   if (hdr[0] != MAGIC || hdr[1] != (c->fp32 ? 1 : 0) || hdr[2] != c->cfg.nx || hdr[3] != c->cfg.ny ||
-      hdr[4] != c->L.n_tiles || hdr[5] != dg2k::TX || hdr[6] != dg2k::TY)
+      hdr[4] != c->L.n_tiles || hdr[5] != c->L.tx || hdr[6] != c->L.ty)
     return fail(c, DG2_E_STATE, "state blob does not match this context");
   int rc = pull_ctrl(c);
   if (rc) return rc;
@@ -603,11 +606,12 @@ int dg2_kernel_info(const dg2_ctx* c, int32_t* tile_x, int32_t* tile_y, int32_t*
                     int32_t* lds_bytes) {
   if (!c) return DG2_E_ARG;
   const int rs = c->fp32 ? 4 : 8;
-  if (tile_x) *tile_x = dg2k::TX;
-  if (tile_y) *tile_y = dg2k::TY;
-  if (threads) *threads = dg2k::NT;
+  const int rb = (c->L.tx + 4) * (c->L.ty + 4), vb = (c->L.tx + 5) * (c->L.ty + 5);
+  if (tile_x) *tile_x = c->L.tx;
+  if (tile_y) *tile_y = c->L.ty;
+  if (threads) *threads = c->L.threads;
   if (blocks) *blocks = c->L.grid;
-  if (lds_bytes) *lds_bytes = 12 * dg2k::RB * rs + dg2k::RB + (dg2k::NT / 64) * 4 * 8;
+  if (lds_bytes) *lds_bytes = (12 * rb + vb) * rs + rb + (c->L.threads / 64) * 4 * 8;
   return DG2_OK;
 }
 

@@ -20,13 +20,34 @@
 
 namespace dg2k {
 
-constexpr int TX = 32;            // tile width (cells, x fastest in memory)
-constexpr int TY = 8;             // tile height
-constexpr int NT = TX * TY;       // threads per block, one cell each
-constexpr int RX = TX + 4;        // LDS box with a 2-cell halo
-constexpr int RY = TY + 4;
-constexpr int RB = RX * RY;
-constexpr int NRING = 2 * (TX + TY);  // non-corner cells of the first halo ring
+// tile shape per precision (cells; x fastest in memory), overridable at build time
+#ifndef DG2_TILE64_X
+#define DG2_TILE64_X 16
+#endif
+#ifndef DG2_TILE64_Y
+#define DG2_TILE64_Y 16
+#endif
+#ifndef DG2_TILE32_X
+#define DG2_TILE32_X 64
+#endif
+#ifndef DG2_TILE32_Y
+#define DG2_TILE32_Y 8
+#endif
+template <typename R> struct Tile;
+template <> struct Tile<double> { static constexpr int X = DG2_TILE64_X, Y = DG2_TILE64_Y; };
+template <> struct Tile<float> { static constexpr int X = DG2_TILE32_X, Y = DG2_TILE32_Y; };
+
+// LDS geometry of a tile: the cell box has a 2-cell halo, the vertex box one more
+template <typename R>
+struct Geo {
+  static constexpr int TX = Tile<R>::X, TY = Tile<R>::Y;
+  static constexpr int NT = TX * TY;           // threads per block, one cell each
+  static constexpr int RX = TX + 4, RY = TY + 4, RB = RX * RY;
+  static constexpr int VX = TX + 5, VY = TY + 5, VB = VX * VY;
+  static constexpr int NRING = 2 * (TX + TY);  // non-corner cells of the first halo ring
+  static_assert(NT % 64 == 0 && NT <= 1024 && NRING <= NT,
+                "tile must give whole waves and one ring cell per thread at most");
+};
 constexpr int NXCD = 8;
 
 constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
@@ -79,16 +100,73 @@ template <> struct K<float> {
 
 __device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+
+// Reciprocal, square root and h^(-1/3) for the inner loops: the hardware estimates
+// (about 23 correct bits for FP64) refined by Newton steps to full FP64 precision
+// (within a few ulp, not correctly rounded); FP32 uses the 1-ulp hardware results.
+__device__ __forceinline__ double frcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float frcp(float d) { return __builtin_amdgcn_rcpf(d); }
+
+__device__ __forceinline__ double fsqrt(double x) {
+  if (!(x > 0.0)) return 0.0;
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * y;
+  double s = x * y;                       // sqrt estimate
+  double r = __builtin_fma(-s, h, 0.5);   // Goldschmidt refinement
+  s = __builtin_fma(s, r, s);
+  h = __builtin_fma(h, r, h);
+  r = __builtin_fma(-s, s, x);
+  return __builtin_fma(r, h, s);
+}
+__device__ __forceinline__ float fsqrt(float x) { return x > 0.0f ? __builtin_sqrtf(x) : 0.0f; }
+
+// y = h^(-1/3) for h > 0: a float log2/exp2 seed, then Newton on y^-3 = h,
+// y <- y (4 - h y^3) / 3, which doubles the correct bits each step
+__device__ __forceinline__ double finvcbrt(double h) {
+  if (!(h >= 1e-30)) return 1.0 / cbrt(h);
+  const float hf = float(h);
+  double y = double(__builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf(hf)));
+  const double third = 0.33333333333333333333;
+  y = y * (4.0 - h * (y * y * y)) * third;
+  y = y * (4.0 - h * (y * y * y)) * third;
+  return y;
+}
+__device__ __forceinline__ float finvcbrt(float h) {
+  if (!(h >= 1e-30f)) return 1.0f / cbrtf(h);
+  float y = __builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf(h));
+  return y * (4.0f - h * (y * y * y)) * 0.333333343f;
+}
 __device__ __forceinline__ double dcbrt(double x) { return cbrt(x); }
 __device__ __forceinline__ float dcbrt(float x) { return cbrtf(x); }
 __device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
 
+// the larger of x and 0 / the smaller of two values, as single min/max instructions
+template <typename R> __device__ __forceinline__ R fmax0(R x) { return __builtin_fmax(x, R(0)); }
+__device__ __forceinline__ float fmax0(float x) { return __builtin_fmaxf(x, 0.0f); }
+__device__ __forceinline__ double fminr(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float fminr(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double fmaxr(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float fmaxr(float a, float b) { return __builtin_fmaxf(a, b); }
+
+// a positive floor for reciprocals whose result is discarded when the argument is not
+// positive (keeps the arithmetic finite without a branch)
+template <typename R> struct Tiny;
+template <> struct Tiny<double> { static constexpr double v = 1e-300; };
+template <> struct Tiny<float> { static constexpr float v = 1e-30f; };
+
+// minmod of three: the smallest magnitude if all three share a sign, else 0, as
+// max(min(a,b,c),0) + min(max(a,b,c),0) (one term is always zero; the sum is exact)
 template <typename R>
 __device__ __forceinline__ R minmod3(R a, R b, R c) {
-  if (a > R(0) && b > R(0) && c > R(0)) return a < b ? (a < c ? a : c) : (b < c ? b : c);
-  if (a < R(0) && b < R(0) && c < R(0)) return a > b ? (a > c ? a : c) : (b > c ? b : c);
-  return R(0);
+  const R lo = fminr(a, fminr(b, c)), hi = fmaxr(a, fmaxr(b, c));
+  return fmaxr(lo, R(0)) + fminr(hi, R(0));
 }
 
 // Q(t) of an inflow segment: linear between knots, held outside them
@@ -125,75 +203,54 @@ struct Side {
   R h, u, v, z;
 };
 
+// revision of one side's limit (h, qx, qy) with this side's bed zb and the face's
+// z* = zs: h* = max(0, eta - z*), velocities from the unrevised depth (zero at or
+// below h_tol), z** = min(z*, eta)
 template <typename R>
 __device__ __forceinline__ Side<R> revise(R h, R qx, R qy, R zb, R zs, R ht) {
   Side<R> s;
   const R eta = h + zb;
-  const R d = eta - zs;
-  s.h = d > R(0) ? d : R(0);
-  if (h > ht) {
-    const R r = R(1) / h;
-    s.u = qx * r;
-    s.v = qy * r;
-  } else {
-    s.u = R(0);
-    s.v = R(0);
-  }
-  s.z = eta < zs ? eta : zs;
+  s.h = fmax0(eta - zs);
+  const bool wet = h > ht;
+  const R r = frcp(fmaxr(h, Tiny<R>::v));
+  s.u = wet ? qx * r : R(0);
+  s.v = wet ? qy * r : R(0);
+  s.z = fminr(eta, zs);
   return s;
 }
 
 // HLL flux through a face, normal frame: (h, un, ut) on each side ->
-// [mass, normal momentum, tangential momentum]
+// [mass, normal momentum, tangential momentum]; wave speeds of the two-rarefaction
+// estimate, the dry-bed front speeds where a side is exactly dry
 template <typename R>
 __device__ __forceinline__ void hll(R g, R hL, R unL, R utL, R hR, R unR, R utR, R f[3]) {
-  if (!(hL > R(0)) && !(hR > R(0))) {
-    f[0] = f[1] = f[2] = R(0);
-    return;
-  }
-  const R cL = dsqrt(g * hL), cR = dsqrt(g * hR);
-  R sL, sR;
-  if (!(hL > R(0))) {
-    sL = unR - R(2) * cR;
-    sR = unR + cR;
-  } else if (!(hR > R(0))) {
-    sL = unL - cL;
-    sR = unL + R(2) * cL;
-  } else {
-    const R us = R(0.5) * (unL + unR) + cL - cR;
-    const R cs = R(0.5) * (cL + cR) + R(0.25) * (unL - unR);
-    const R a = unL - cL, b = us - cs, c = unR + cR, d = us + cs;
-    sL = a < b ? a : b;
-    sR = c > d ? c : d;
-  }
+  const bool wL = hL > R(0), wR = hR > R(0);
+  const R cL = fsqrt(g * hL), cR = fsqrt(g * hR);
+  const R us = R(0.5) * (unL + unR) + cL - cR;
+  const R cs = R(0.5) * (cL + cR) + R(0.25) * (unL - unR);
+  const R sLw = fminr(unL - cL, us - cs), sRw = fmaxr(unR + cR, us + cs);
+  const R sL = wL ? (wR ? sLw : unL - cL) : unR - R(2) * cR;
+  const R sR = wL ? (wR ? sRw : unL + R(2) * cL) : unR + cR;
   const R qL = hL * unL, qR = hR * unR;
-  const R pL = R(0.5) * g * hL * hL, pR = R(0.5) * g * hR * hR;
-  if (sL >= R(0)) {
-    f[0] = qL;
-    f[1] = qL * unL + pL;
-    f[2] = qL * utL;
-  } else if (sR <= R(0)) {
-    f[0] = qR;
-    f[1] = qR * unR + pR;
-    f[2] = qR * utR;
-  } else {
-    const R inv = R(1) / (sR - sL);
-    const R ss = sL * sR;
-    f[0] = (sR * qL - sL * qR + ss * (hR - hL)) * inv;
-    f[1] = (sR * (qL * unL + pL) - sL * (qR * unR + pR) + ss * (qR - qL)) * inv;
-    f[2] = (sR * qL * utL - sL * qR * utR + ss * (hR * utR - hL * utL)) * inv;
-  }
+  const R FL0 = qL, FL1 = qL * unL + R(0.5) * g * hL * hL, FL2 = qL * utL;
+  const R FR0 = qR, FR1 = qR * unR + R(0.5) * g * hR * hR, FR2 = qR * utR;
+  const R inv = frcp(fmaxr(sR - sL, Tiny<R>::v));
+  const R ss = sL * sR;
+  const R S0 = (sR * FL0 - sL * FR0 + ss * (hR - hL)) * inv;
+  const R S1 = (sR * FL1 - sL * FR1 + ss * (qR - qL)) * inv;
+  const R S2 = (sR * FL2 - sL * FR2 + ss * (hR * utR - hL * utL)) * inv;
+  const bool up = sL >= R(0), dn = sR <= R(0), dry = !wL && !wR;
+  f[0] = dry ? R(0) : (up ? FL0 : (dn ? FR0 : S0));
+  f[1] = dry ? R(0) : (up ? FL1 : (dn ? FR1 : S1));
+  f[2] = dry ? R(0) : (up ? FL2 : (dn ? FR2 : S2));
 }
 
 // physical flux along a normal at a Gauss point, velocities zero at or below h_tol
 template <typename R>
 __device__ __forceinline__ void gauss_flux(R g, R ht, R h, R qn, R qt, R f[3]) {
-  R un = R(0), ut = R(0);
-  if (h > ht) {
-    const R r = R(1) / h;
-    un = qn * r;
-    ut = qt * r;
-  }
+  const bool wet = h > ht;
+  const R r = frcp(fmaxr(h, Tiny<R>::v));
+  const R un = wet ? qn * r : R(0), ut = wet ? qt * r : R(0);
   const R q = h * un;
   f[0] = q;
   f[1] = q * un + R(0.5) * g * h * h;
@@ -202,22 +259,24 @@ __device__ __forceinline__ void gauss_flux(R g, R ht, R h, R qn, R qt, R f[3]) {
 
 // Split-implicit Manning increment at one point: with w = dt g n^2 h^(-4/3) and
 // s = |u|, the Newton step of backward Euler with the diagonal Jacobian gives
-// dqx = -qx w s / (1 + w (2u^2 + v^2) / s), and likewise for qy.
+// dqx = -qx w s / (1 + w (2u^2 + v^2) / s), and likewise for qy. Zero where h <= h_tol
+// or the water is still.
 template <typename R>
 __device__ __forceinline__ void friction_inc(R gn2dt, R ht, R h, R qx, R qy, R& dqx, R& dqy) {
-  dqx = R(0);
-  dqy = R(0);
-  if (!(h > ht)) return;
-  const R r = R(1) / h;
-  const R u = qx * r, v = qy * r;
+  const bool wet = h > ht;
+  const R y = finvcbrt(wet ? h : R(1));  // h^(-1/3)
+  const R y3 = y * y * y;                // 1/h
+  const R u = qx * y3, v = qy * y3;
   const R s2 = u * u + v * v;
-  if (!(s2 > R(0))) return;
-  const R rs = R(1) / dsqrt(s2);
-  const R w = gn2dt * r / dcbrt(h);
+  const bool act = wet && s2 > R(0);
+  const R rs = frcp(fsqrt(fmaxr(s2, Tiny<R>::v)));
+  const R w = gn2dt * (y3 * y);          // dt g n^2 h^(-4/3)
   const R a = w * u * u * rs, b = w * v * v * rs;
   const R ab = a + b;
-  dqx = -qx * ab / (R(1) + R(2) * a + b);
-  dqy = -qy * ab / (R(1) + a + R(2) * b);
+  const R d1 = R(1) + R(2) * a + b, d2 = R(1) + a + R(2) * b;
+  const R inv = frcp(d1 * d2);
+  dqx = act ? -qx * ab * d2 * inv : R(0);
+  dqy = act ? -qy * ab * d1 * inv : R(0);
 }
 
 template <typename R>
@@ -266,19 +325,19 @@ __device__ __forceinline__ void ghost(const Params<R>& p, int code, double t, bo
 // hmax the largest of the mean and the two face limits in that direction; +inf if dry
 template <typename R>
 __device__ __forceinline__ double cell_dtc(const Params<R>& p, R h0, R h1x, R h1y, R qx0, R qy0) {
-  if (!(h0 > p.h_tol)) return __longlong_as_double((long long)INF_BITS);
-  const R u = qx0 / h0, v = qy0 / h0;
-  const R a = p.dx / (dabs(u) + dsqrt(p.g * (h0 + K<R>::s3 * dabs(h1x))));
-  const R b = p.dx / (dabs(v) + dsqrt(p.g * (h0 + K<R>::s3 * dabs(h1y))));
-  return double(a < b ? a : b);
+  const R r = frcp(fmaxr(h0, Tiny<R>::v));
+  const R u = qx0 * r, v = qy0 * r;
+  const R a = p.dx * frcp(dabs(u) + fsqrt(p.g * (h0 + K<R>::s3 * dabs(h1x))));
+  const R b = p.dx * frcp(dabs(v) + fsqrt(p.g * (h0 + K<R>::s3 * dabs(h1y))));
+  return h0 > p.h_tol ? double(fminr(a, b)) : __longlong_as_double((long long)INF_BITS);
 }
 
 // magnitude cap of a face-limit velocity component: the larger neighbouring mean
 // velocity magnitude plus the velocity scale of the dry tolerance
 template <typename R>
 __device__ __forceinline__ R vcap(R x, R a, R b, R slack) {
-  const R m = (dabs(a) > dabs(b) ? dabs(a) : dabs(b)) + slack;
-  return x > m ? m : (x < -m ? -m : x);
+  const R m = fmaxr(dabs(a), dabs(b)) + slack;
+  return fminr(fmaxr(x, -m), m);
 }
 
 // CFL candidate of the boundary forcing at time t (critical-depth inflow, fixed state)
@@ -325,58 +384,57 @@ __device__ __forceinline__ double wave_min(double x) {
 // ---------------------------------------------------------------------------------
 // the stage kernel
 // ---------------------------------------------------------------------------------
-template <typename R, int STAGE>
-__global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
-  const int b = blockIdx.x;
-  const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
-  if (tile >= p.n_tiles) return;
+template <typename R>
+struct Smem {
+  R c[9][Geo<R>::RB];   // halo box coefficients; later face states and fluxes
+  R zv[Geo<R>::VB];     // bed vertices of the box
+  R z0[Geo<R>::RB];     // bed means of the box cells
+  R um[Geo<R>::RB];     // mean velocities (zero at or below h_tol)
+  R vm[Geo<R>::RB];
+  unsigned char flag[Geo<R>::RB];  // 1: first-order (front) cell
+  double red[Geo<R>::NT / 64][4];
+};
+
+// One stage over one tile. EDGE is false for tiles whose halo box lies inside the
+// domain: no clamping, no boundary faces, every cell active.
+template <typename R, int STAGE, bool EDGE>
+__device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, const int tile,
+                                           const int i0, const int j0, const double t,
+                                           const double dt, const double t_next) {
+  constexpr int TX = Geo<R>::TX, TY = Geo<R>::TY, NT = Geo<R>::NT;
+  constexpr int RX = Geo<R>::RX, RB = Geo<R>::RB, VX = Geo<R>::VX, VB = Geo<R>::VB;
+  constexpr int NRING = Geo<R>::NRING;
   const int tid = threadIdx.x;
-  const int i0 = (tile % p.tiles_x) * TX, j0 = (tile / p.tiles_x) * TY;
   const int nx = p.nx, ny = p.ny;
   const long long n = p.n;
   const R ht = p.h_tol;
+  const R s3 = K<R>::s3;
 
-  double t, dt, t_next, dt_cfl;
-  step_time(p, t, dt, t_next, dt_cfl);
-
-  // own cell
   const int ci = i0 + tid % TX, cj = j0 + tid / TX;
-  const bool active = ci < nx && cj < ny;
-  const long long ck = (long long)cj * nx + ci;
+  const bool active = !EDGE || (ci < nx && cj < ny);
+  const unsigned ck = (unsigned)(cj * nx + ci);
 
-  if (!(dt > 0.0)) {  // the run has reached t_end: carry the state over unchanged
-    if (STAGE == 1) {
-      if (active)
-        for (int q = 0; q < 9; ++q) p.vbuf[q * n + ck] = p.uin[q * n + ck];
-      if (tile == 0 && tid == 0) {
-        Ctrl* c = p.ctrl;
-        const int a = p.parity, o = 1 - p.parity;
-        c->t[o] = c->t[a];
-        c->step[o] = c->step[a];
-        c->dtc[o] = c->dtc[a];
-        c->dt_used[a] = 0.0;
-      }
+  // stage 2 needs V^n of the own cell only at the end; FP32 has the registers to
+  // issue its loads now
+  constexpr bool kPrefetch = sizeof(R) == 4;
+  R vn[9];
+  if (STAGE == 2 && kPrefetch && active) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) vn[q] = (p.vbuf + q * n)[ck];
+  }
+
+  // ---- phase 1: the box (friction applied in stage 1) and its bed vertices ----
+  // vertex (iv, jv) sits at box position (iv - i0 + 2, jv - j0 + 2); a clamped halo
+  // cell only uses vertices of in-domain cells, which lie in the box
+  for (int r = tid; r < VB; r += NT) {
+    int iv = i0 - 2 + r % VX, jv = j0 - 2 + r / VX;
+    if (EDGE) {
+      iv = iv < 0 ? 0 : (iv > nx ? nx : iv);
+      jv = jv < 0 ? 0 : (jv > ny ? ny : jv);
     }
-    return;
+    sm.zv[r] = p.zv[(unsigned)(jv * (nx + 1) + iv)];
   }
-  if (STAGE == 1 && tile == 0 && tid == 0) {
-    Ctrl* c = p.ctrl;
-    const int a = p.parity, o = 1 - p.parity;
-    c->t[o] = t_next;
-    c->step[o] = c->step[a] + 1;
-    c->dtc[o] = INF_BITS;
-    c->dt_used[a] = dt;
-    if (dt_cfl < 1e-12) atomicOr(&c->health, 2);
-  }
-
-  __shared__ R s_c[9][RB];   // halo box coefficients; later face states and fluxes
-  __shared__ R s_z0[RB];
-  __shared__ R s_um[RB];  // mean velocities (zero at or below h_tol)
-  __shared__ R s_vm[RB];
-  __shared__ unsigned char s_flag[RB];
-  __shared__ double s_red[NT / 64][4];
-
-  // ---- phase 1: load the box (friction applied in stage 1) ----
+  auto zb = [&](int iv, int jv) -> R { return sm.zv[(jv - j0 + 2) * VX + (iv - i0 + 2)]; };
   const R dtr = R(dt);
   for (int r = tid; r < RB; r += NT) {
     const int a = r % RX, bb = r / RX;
@@ -384,16 +442,15 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
     const bool corner = (a == 1 || a == TX + 2) && (bb == 1 || bb == TY + 2);
     if (!(inx || iny || corner)) continue;
     int i = i0 - 2 + a, j = j0 - 2 + bb;
-    i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
-    j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
-    const long long k = (long long)j * nx + i;
+    if (EDGE) {
+      i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+      j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
+    }
+    const unsigned k = (unsigned)(j * nx + i);
     R c[9];
     const R* __restrict__ src = STAGE == 1 ? p.uin : p.ui;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) c[q] = src[q * n + k];
-    const R sw = zvat(p, i, j), se = zvat(p, i + 1, j);
-    const R nw = zvat(p, i, j + 1), ne = zvat(p, i + 1, j + 1);
-    s_z0[r] = R(0.25) * ((ne + sw) + (nw + se));
+    for (int q = 0; q < 9; ++q) c[q] = (src + q * n)[k];
     if (STAGE == 1 && !corner) {
       const R nm = p.manning ? p.manning[k] : p.n_scalar;
       if (nm > R(0)) {
@@ -421,20 +478,26 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
       }
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) s_c[q][r] = c[q];
-    R um = R(0), vm = R(0);
-    if (c[0] > ht) {
-      const R rh = R(1) / c[0];
-      um = c[3] * rh;
-      vm = c[6] * rh;
+    for (int q = 0; q < 9; ++q) sm.c[q][r] = c[q];
+    const bool wet = c[0] > ht;
+    const R rh = frcp(fmaxr(c[0], Tiny<R>::v));
+    sm.um[r] = wet ? c[3] * rh : R(0);
+    sm.vm[r] = wet ? c[6] * rh : R(0);
+  }
+  __syncthreads();
+  for (int r = tid; r < RB; r += NT) {  // bed means of the box cells (eq 8, diagonal pairs)
+    int i = i0 - 2 + r % RX, j = j0 - 2 + r / RX;
+    if (EDGE) {
+      i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+      j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
     }
-    s_um[r] = um;
-    s_vm[r] = vm;
+    sm.z0[r] = R(0.25) * ((zb(i + 1, j + 1) + zb(i, j)) + (zb(i, j + 1) + zb(i + 1, j)));
   }
   __syncthreads();
 
   // ---- phase 2a: front flags and the limiter ----
-  // item A: the own cell (both directions); item B: one first-ring cell (one direction)
+  // item A: the own cell (both directions); item B: one first-ring cell (its slope
+  // across the tile edge; the depth slope in both directions for the front test)
   const int ca = tid % TX + 2, cb = tid / TX + 2;
   const int cpos = cb * RX + ca;
   const bool has_b = tid < NRING;
@@ -447,48 +510,49 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
   }
   const int rpos = rb_b * RX + rb_a;
   const int ri = i0 - 2 + rb_a, rj = j0 - 2 + rb_b;
-  const bool b_in = has_b && ri >= 0 && ri < nx && rj >= 0 && rj < ny;
+  const bool b_in = has_b && (!EDGE || (ri >= 0 && ri < nx && rj >= 0 && rj < ny));
 
   auto limit_cell = [&](int pos, int i, int j, int dirs, R v[9]) -> unsigned char {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) v[q] = s_c[q][pos];
+    for (int q = 0; q < 9; ++q) v[q] = sm.c[q][pos];
     const R h0 = v[0];
     if (!(h0 > R(0))) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) v[q] = R(0);
       return 1;
     }
-    const bool front = !(h0 > ht) || !(s_c[0][pos - 1] > ht) || !(s_c[0][pos + 1] > ht) ||
-                       !(s_c[0][pos - RX] > ht) || !(s_c[0][pos + RX] > ht);
+    const bool front = !(h0 > ht) || !(sm.c[0][pos - 1] > ht) || !(sm.c[0][pos + 1] > ht) ||
+                       !(sm.c[0][pos - RX] > ht) || !(sm.c[0][pos + RX] > ht);
     if (front) {
       v[1] = v[2] = v[4] = v[5] = v[7] = v[8] = R(0);
       return 1;
     }
     if (p.limiter) {
-      R z0, z1x, z1y;
-      bed(p, i, j, z0, z1x, z1y);
-      const R e0 = h0 + s_z0[pos];
+      const R sw = zb(i, j), se = zb(i + 1, j), nw = zb(i, j + 1), ne = zb(i + 1, j + 1);
+      const R z1x = (R(0.5) * (ne + se) - R(0.5) * (nw + sw)) * K<R>::inv_2s3;
+      const R z1y = (R(0.5) * (nw + ne) - R(0.5) * (sw + se)) * K<R>::inv_2s3;
+      const R e0 = h0 + sm.z0[pos];
 #pragma unroll
       for (int d = 1; d <= 2; ++d) {
         const int off = d == 1 ? 1 : RX;
         const R zs = d == 1 ? z1x : z1y;
-        const R em = s_c[0][pos - off] + s_z0[pos - off];
-        const R ep = s_c[0][pos + off] + s_z0[pos + off];
+        const R em = sm.c[0][pos - off] + sm.z0[pos - off];
+        const R ep = sm.c[0][pos + off] + sm.z0[pos + off];
         const R e1 = v[d] + zs;
         const R le = minmod3(e1, (ep - e0) * K<R>::inv_s3, (e0 - em) * K<R>::inv_s3);
-        if (le != e1) v[d] = le - zs;
+        v[d] = le != e1 ? le - zs : v[d];
         if (!(dirs & d)) continue;  // discharge slopes only where they are used
 #pragma unroll
         for (int var = 1; var <= 2; ++var) {
           const int q0 = 3 * var;
           const R a0 = v[q0];
-          const R am = s_c[q0][pos - off], ap = s_c[q0][pos + off];
+          const R am = sm.c[q0][pos - off], ap = sm.c[q0][pos + off];
           v[q0 + d] = minmod3(v[q0 + d], (ap - a0) * K<R>::inv_s3, (a0 - am) * K<R>::inv_s3);
         }
       }
     }
     // a depth plane negative at a face centre: a front inside the cell
-    if (h0 - K<R>::s3 * dabs(v[1]) < R(0) || h0 - K<R>::s3 * dabs(v[2]) < R(0)) {
+    if (h0 - s3 * dabs(v[1]) < R(0) || h0 - s3 * dabs(v[2]) < R(0)) {
       v[1] = v[2] = v[4] = v[5] = v[7] = v[8] = R(0);
       return 1;
     }
@@ -496,52 +560,53 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
   };
 
   R va[9];
-  if (active && s_c[0][cpos] != s_c[0][cpos]) atomicOr(&p.ctrl->health, 1);  // NaN depth
-  const unsigned char fa = limit_cell(cpos, active ? ci : 0, active ? cj : 0, 3, va);
+  if (active) {  // a NaN anywhere in the cell's input would otherwise be absorbed
+    R sum = R(0);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sum += sm.c[q][cpos];
+    if (sum != sum) atomicOr(&p.ctrl->health, 1);
+  }
+  const unsigned char fa = limit_cell(cpos, active ? ci : i0, active ? cj : j0, 3, va);
   R vb[9];
   unsigned char fb = 1;
   if (b_in) fb = limit_cell(rpos, ri, rj, rb_dir, vb);
-  s_flag[cpos] = fa;
-  if (has_b) s_flag[rpos] = fb;
+  sm.flag[cpos] = fa;
+  if (has_b) sm.flag[rpos] = fb;
   __syncthreads();  // box reads are done and the flags are visible
 
   // ---- phase 2b: revised face states ----
   // own cell: W, E, S, N sides (kept); E and N sides published for the neighbours
-  R* const s_side = &s_c[0][0];  // planes 0..2: east side (h, u, v); 3..5: north side
+  R* const s_side = &sm.c[0][0];  // planes 0..2: east side (h, u, v); 3..5: north side
   Side<R> sw_, se_, ss_, sn_;
-  const R s3 = K<R>::s3;
   const R slack = R(dsqrt(p.gd * p.htd));
-  auto zside = [&](int pos, int i, int j, R zf) -> R {
-    // bed of the side at position pos: flat at z0 for a first-order cell
-    (void)i; (void)j;
-    return s_flag[pos] ? s_z0[pos] : zf;
-  };
+  auto zside = [&](int pos, R zf) -> R { return sm.flag[pos] ? sm.z0[pos] : zf; };
   if (active) {
-    const R zW = R(0.5) * (zvat(p, ci, cj + 1) + zvat(p, ci, cj));
-    const R zE = R(0.5) * (zvat(p, ci + 1, cj + 1) + zvat(p, ci + 1, cj));
-    const R zS = R(0.5) * (zvat(p, ci, cj) + zvat(p, ci + 1, cj));
-    const R zN = R(0.5) * (zvat(p, ci, cj + 1) + zvat(p, ci + 1, cj + 1));
-    const R own_w = fa ? s_z0[cpos] : zW, own_e = fa ? s_z0[cpos] : zE;
-    const R own_s = fa ? s_z0[cpos] : zS, own_n = fa ? s_z0[cpos] : zN;
-    const R nb_w = ci > 0 ? zside(cpos - 1, ci - 1, cj, zW) : own_w;
-    const R nb_e = ci < nx - 1 ? zside(cpos + 1, ci + 1, cj, zE) : own_e;
-    const R nb_s = cj > 0 ? zside(cpos - RX, ci, cj - 1, zS) : own_s;
-    const R nb_n = cj < ny - 1 ? zside(cpos + RX, ci, cj + 1, zN) : own_n;
+    const R zW = R(0.5) * (zb(ci, cj + 1) + zb(ci, cj));
+    const R zE = R(0.5) * (zb(ci + 1, cj + 1) + zb(ci + 1, cj));
+    const R zS = R(0.5) * (zb(ci, cj) + zb(ci + 1, cj));
+    const R zN = R(0.5) * (zb(ci, cj + 1) + zb(ci + 1, cj + 1));
+    const R z0c = sm.z0[cpos];
+    const R own_w = fa ? z0c : zW, own_e = fa ? z0c : zE;
+    const R own_s = fa ? z0c : zS, own_n = fa ? z0c : zN;
+    const R nb_w = (!EDGE || ci > 0) ? zside(cpos - 1, zW) : own_w;
+    const R nb_e = (!EDGE || ci < nx - 1) ? zside(cpos + 1, zE) : own_e;
+    const R nb_s = (!EDGE || cj > 0) ? zside(cpos - RX, zS) : own_s;
+    const R nb_n = (!EDGE || cj < ny - 1) ? zside(cpos + RX, zN) : own_n;
     sw_ = revise(va[0] - s3 * va[1], va[3] - s3 * va[4], va[6] - s3 * va[7], own_w,
-                 own_w > nb_w ? own_w : nb_w, ht);
+                 fmaxr(own_w, nb_w), ht);
     se_ = revise(va[0] + s3 * va[1], va[3] + s3 * va[4], va[6] + s3 * va[7], own_e,
-                 own_e > nb_e ? own_e : nb_e, ht);
+                 fmaxr(own_e, nb_e), ht);
     ss_ = revise(va[0] - s3 * va[2], va[3] - s3 * va[5], va[6] - s3 * va[8], own_s,
-                 own_s > nb_s ? own_s : nb_s, ht);
+                 fmaxr(own_s, nb_s), ht);
     sn_ = revise(va[0] + s3 * va[2], va[3] + s3 * va[5], va[6] + s3 * va[8], own_n,
-                 own_n > nb_n ? own_n : nb_n, ht);
-    const R u0 = s_um[cpos], v0 = s_vm[cpos];
-    const int pw = ci > 0 ? cpos - 1 : cpos, pe = ci < nx - 1 ? cpos + 1 : cpos;
-    const int ps = cj > 0 ? cpos - RX : cpos, pn = cj < ny - 1 ? cpos + RX : cpos;
-    sw_.u = vcap(sw_.u, u0, s_um[pw], slack); sw_.v = vcap(sw_.v, v0, s_vm[pw], slack);
-    se_.u = vcap(se_.u, u0, s_um[pe], slack); se_.v = vcap(se_.v, v0, s_vm[pe], slack);
-    ss_.u = vcap(ss_.u, u0, s_um[ps], slack); ss_.v = vcap(ss_.v, v0, s_vm[ps], slack);
-    sn_.u = vcap(sn_.u, u0, s_um[pn], slack); sn_.v = vcap(sn_.v, v0, s_vm[pn], slack);
+                 fmaxr(own_n, nb_n), ht);
+    const R u0 = sm.um[cpos], v0 = sm.vm[cpos];
+    const int pw = (!EDGE || ci > 0) ? cpos - 1 : cpos, pe = (!EDGE || ci < nx - 1) ? cpos + 1 : cpos;
+    const int ps = (!EDGE || cj > 0) ? cpos - RX : cpos, pn = (!EDGE || cj < ny - 1) ? cpos + RX : cpos;
+    sw_.u = vcap(sw_.u, u0, sm.um[pw], slack); sw_.v = vcap(sw_.v, v0, sm.vm[pw], slack);
+    se_.u = vcap(se_.u, u0, sm.um[pe], slack); se_.v = vcap(se_.v, v0, sm.vm[pe], slack);
+    ss_.u = vcap(ss_.u, u0, sm.um[ps], slack); ss_.v = vcap(ss_.v, v0, sm.vm[ps], slack);
+    sn_.u = vcap(sn_.u, u0, sm.um[pn], slack); sn_.v = vcap(sn_.v, v0, sm.vm[pn], slack);
   }
   // ring item: W ring publishes its east side, S ring its north side; E and N ring
   // cells keep their west / south side for the tile's east / north faces
@@ -553,18 +618,19 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
     const int npos = rpos + oa + ob * RX;  // the tile cell across the face
     const int ni = ri + oa, nj = rj + ob;
     R zf;
-    if (rb_side == 0) zf = R(0.5) * (zvat(p, ri + 1, rj + 1) + zvat(p, ri + 1, rj));
-    else if (rb_side == 1) zf = R(0.5) * (zvat(p, ri, rj + 1) + zvat(p, ri, rj));
-    else if (rb_side == 2) zf = R(0.5) * (zvat(p, ri, rj + 1) + zvat(p, ri + 1, rj + 1));
-    else zf = R(0.5) * (zvat(p, ri, rj) + zvat(p, ri + 1, rj));
-    const R own = fb ? s_z0[rpos] : zf;
-    const R nb = (ni >= 0 && ni < nx && nj >= 0 && nj < ny) ? zside(npos, ni, nj, zf) : own;
-    const R zs = own > nb ? own : nb;
-    const int d = rb_dir;
+    if (rb_side == 0) zf = R(0.5) * (zb(ri + 1, rj + 1) + zb(ri + 1, rj));
+    else if (rb_side == 1) zf = R(0.5) * (zb(ri, rj + 1) + zb(ri, rj));
+    else if (rb_side == 2) zf = R(0.5) * (zb(ri, rj + 1) + zb(ri + 1, rj + 1));
+    else zf = R(0.5) * (zb(ri, rj) + zb(ri + 1, rj));
+    const R own = fb ? sm.z0[rpos] : zf;
+    const R nb = (!EDGE || (ni >= 0 && ni < nx && nj >= 0 && nj < ny)) ? zside(npos, zf) : own;
+    const R zs = fmaxr(own, nb);
+    const bool dx_ = rb_dir == 1;  // select, not index: keeps vb in registers
+    const R h1 = dx_ ? vb[1] : vb[2], qx1 = dx_ ? vb[4] : vb[5], qy1 = dx_ ? vb[7] : vb[8];
     const R sg = (rb_side == 0 || rb_side == 2) ? s3 : -s3;  // toward the tile
-    sb_ = revise(vb[0] + sg * vb[d], vb[3] + sg * vb[3 + d], vb[6] + sg * vb[6 + d], own, zs, ht);
-    sb_.u = vcap(sb_.u, s_um[rpos], s_um[npos], slack);
-    sb_.v = vcap(sb_.v, s_vm[rpos], s_vm[npos], slack);
+    sb_ = revise(vb[0] + sg * h1, vb[3] + sg * qx1, vb[6] + sg * qy1, own, zs, ht);
+    sb_.u = vcap(sb_.u, sm.um[rpos], sm.um[npos], slack);
+    sb_.v = vcap(sb_.v, sm.vm[rpos], sm.vm[npos], slack);
   }
   if (active) {  // s_c is no longer read: it now holds face data
     s_side[0 * RB + cpos] = se_.h;
@@ -594,47 +660,47 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
   R fw[3] = {R(0), R(0), R(0)}, fs[3] = {R(0), R(0), R(0)};
   // x-face at index f between cells f-1 and f on row j; pos is the box position of f
   auto xface = [&](int f, int j, int pos, const Side<R>& own_r, bool have_r, R out[3]) -> bool {
-    if (j >= ny || f > nx) return false;
-    R lh, lu, lv, rh, ru, rv;
-    if (f > 0) {
+    if (EDGE && (j >= ny || f > nx)) return false;
+    R lh = R(0), lu = R(0), lv = R(0), rh = R(0), ru = R(0), rv = R(0);
+    if (!EDGE || f > 0) {
       lh = s_side[0 * RB + pos - 1];
       lu = s_side[1 * RB + pos - 1];
       lv = s_side[2 * RB + pos - 1];
     }
-    if (f < nx) {
+    if (!EDGE || f < nx) {
       if (!have_r) return false;
       rh = own_r.h; ru = own_r.u; rv = own_r.v;
     }
-    if (f == 0) {
+    if (EDGE && f == 0) {
       ghost(p, p.bface[j], t_stage, true, R(1), rh, ru, rv, lh, lu, lv);
-    } else if (f == nx) {
+    } else if (EDGE && f == nx) {
       ghost(p, p.bface[ny + j], t_stage, true, R(-1), lh, lu, lv, rh, ru, rv);
     }
     hll(g, lh, lu, lv, rh, ru, rv, out);
-    if (f == 0) {
+    if (EDGE && f == 0) {
       const double m = double(out[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
-    } else if (f == nx) {
+    } else if (EDGE && f == nx) {
       const double m = -double(out[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
     }
     return true;
   };
   auto yface = [&](int i, int f, int pos, const Side<R>& own_r, bool have_r, R out[3]) -> bool {
-    if (i >= nx || f > ny) return false;
-    R lh, lu, lv, rh, ru, rv;  // (h, normal = v, tangential = u)
-    if (f > 0) {
+    if (EDGE && (i >= nx || f > ny)) return false;
+    R lh = R(0), lu = R(0), lv = R(0), rh = R(0), ru = R(0), rv = R(0);  // (h, normal v, tangential u)
+    if (!EDGE || f > 0) {
       lh = s_side[3 * RB + pos - RX];
-      lu = s_side[5 * RB + pos - RX];  // normal: v
-      lv = s_side[4 * RB + pos - RX];  // tangential: u
+      lu = s_side[5 * RB + pos - RX];
+      lv = s_side[4 * RB + pos - RX];
     }
-    if (f < ny) {
+    if (!EDGE || f < ny) {
       if (!have_r) return false;
       rh = own_r.h; ru = own_r.v; rv = own_r.u;
     }
-    if (f == 0) {
+    if (EDGE && f == 0) {
       ghost(p, p.bface[2 * ny + i], t_stage, false, R(1), rh, ru, rv, lh, lu, lv);
-    } else if (f == ny) {
+    } else if (EDGE && f == ny) {
       ghost(p, p.bface[2 * ny + nx + i], t_stage, false, R(-1), lh, lu, lv, rh, ru, rv);
     }
     R o[3];
@@ -642,10 +708,10 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
     out[0] = o[0];
     out[1] = o[2];  // x-momentum is tangential on a y-face
     out[2] = o[1];
-    if (f == 0) {
+    if (EDGE && f == 0) {
       const double m = double(o[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
-    } else if (f == ny) {
+    } else if (EDGE && f == ny) {
       const double m = -double(o[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
     }
@@ -668,6 +734,10 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
   // ---- phase 3: L, the stage update, and the per-block reductions ----
   double my_dtc = __longlong_as_double((long long)INF_BITS);
   if (active) {
+    if (STAGE == 2 && !kPrefetch) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) vn[q] = (p.vbuf + q * n)[ck];
+    }
     const R fe[3] = {s_side[0 * RB + cpos + 1], s_side[1 * RB + cpos + 1], s_side[2 * RB + cpos + 1]};
     const R fn[3] = {s_side[3 * RB + cpos + RX], s_side[4 * RB + cpos + RX], s_side[5 * RB + cpos + RX]};
     const R idx = R(1) / p.dx;
@@ -713,7 +783,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
       for (int q = 0; q < 9; ++q) u[q] = va[q] + dtr * L[q];
     } else {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) u[q] = R(0.5) * (p.vbuf[q * n + ck] + va[q] + dtr * L[q]);
+      for (int q = 0; q < 9; ++q) u[q] = R(0.5) * (vn[q] + va[q] + dtr * L[q]);
     }
     // after each stage: clip a negative mean depth (booking the mass), then drop the
     // discharge of cells at or below the dry tolerance
@@ -721,43 +791,52 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
       led_clip += -double(u[0]) * p.dxd * p.dxd * (STAGE == 1 ? 0.5 : 1.0);
       u[0] = u[1] = u[2] = R(0);
     }
-    if (!(u[0] > ht)) u[3] = u[4] = u[5] = u[6] = u[7] = u[8] = R(0);
-    bool bad = false;
+    const bool dry = !(u[0] > ht);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) bad |= (u[q] != u[q]);
-    if (bad) atomicOr(&p.ctrl->health, 1);
+    for (int q = 3; q < 9; ++q) u[q] = dry ? R(0) : u[q];
+    R sum = R(0);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sum += u[q];
+    if (sum != sum) atomicOr(&p.ctrl->health, 1);
     if (STAGE == 1) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
-        p.vbuf[q * n + ck] = va[q];
-        p.ui[q * n + ck] = u[q];
+        (p.vbuf + q * n)[ck] = va[q];
+        (p.ui + q * n)[ck] = u[q];
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) p.vbuf[q * n + ck] = u[q];
+      for (int q = 0; q < 9; ++q) (p.vbuf + q * n)[ck] = u[q];
       my_dtc = cell_dtc(p, u[0], u[1], u[2], u[3], u[6]);
     }
   }
 
-  // per-block reductions in a fixed order (deterministic)
+  // per-block reductions in a fixed order (deterministic); ledger terms exist only in
+  // edge tiles (boundary fluxes) or where a depth was clipped
   const int lane = tid & 63, wv = tid >> 6;
-  double r_in = wave_sum(led_in), r_out = wave_sum(led_out), r_clip = wave_sum(led_clip);
-  double r_dt = 0.0;
-  if (STAGE == 2) r_dt = wave_min(my_dtc);
-  if (lane == 0) {
-    s_red[wv][0] = r_in;
-    s_red[wv][1] = r_out;
-    s_red[wv][2] = r_clip;
-    s_red[wv][3] = r_dt;
+  const bool any_led = EDGE || __any(led_clip != 0.0);
+  if (any_led) {
+    const double r_in = wave_sum(led_in), r_out = wave_sum(led_out), r_clip = wave_sum(led_clip);
+    if (lane == 0) {
+      sm.red[wv][0] = r_in;
+      sm.red[wv][1] = r_out;
+      sm.red[wv][2] = r_clip;
+    }
+  } else if (lane == 0) {
+    sm.red[wv][0] = sm.red[wv][1] = sm.red[wv][2] = 0.0;
+  }
+  if (STAGE == 2) {
+    const double r_dt = wave_min(my_dtc);
+    if (lane == 0) sm.red[wv][3] = r_dt;
   }
   __syncthreads();
   if (tid == 0) {
     double a = 0, bsum = 0, c = 0, m = __longlong_as_double((long long)INF_BITS);
     for (int w = 0; w < NT / 64; ++w) {
-      a += s_red[w][0];
-      bsum += s_red[w][1];
-      c += s_red[w][2];
-      if (STAGE == 2) m = s_red[w][3] < m ? s_red[w][3] : m;
+      a += sm.red[w][0];
+      bsum += sm.red[w][1];
+      c += sm.red[w][2];
+      if (STAGE == 2) m = sm.red[w][3] < m ? sm.red[w][3] : m;
     }
     if (a != 0.0 || bsum != 0.0 || c != 0.0) {
       double* led = p.ledger + 4 * (long long)tile;
@@ -774,6 +853,59 @@ __global__ __launch_bounds__(NT) void stage_kernel(Params<R> p) {
         atomicMin(&p.ctrl->dtc[1 - p.parity], (unsigned long long)__double_as_longlong(m));
     }
   }
+}
+
+#ifndef DG2_MIN_WAVES
+#define DG2_MIN_WAVES 1
+#endif
+template <typename R, int STAGE>
+__global__ __launch_bounds__(Geo<R>::NT) __attribute__((amdgpu_waves_per_eu(DG2_MIN_WAVES)))
+void stage_kernel(Params<R> p) {
+  constexpr int TX = Geo<R>::TX, TY = Geo<R>::TY;
+  const int b = blockIdx.x;
+  const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
+  if (tile >= p.n_tiles) return;
+  const int tid = threadIdx.x;
+  const int i0 = (tile % p.tiles_x) * TX, j0 = (tile / p.tiles_x) * TY;
+  const long long n = p.n;
+
+  double t, dt, t_next, dt_cfl;
+  step_time(p, t, dt, t_next, dt_cfl);
+
+  if (!(dt > 0.0)) {  // the run has reached t_end: carry the state over unchanged
+    if (STAGE == 1) {
+      const int ci = i0 + tid % TX, cj = j0 + tid / TX;
+      if (ci < p.nx && cj < p.ny) {
+        const unsigned ck = (unsigned)(cj * p.nx + ci);
+        for (int q = 0; q < 9; ++q) (p.vbuf + q * n)[ck] = (p.uin + q * n)[ck];
+      }
+      if (tile == 0 && tid == 0) {
+        Ctrl* c = p.ctrl;
+        const int a = p.parity, o = 1 - p.parity;
+        c->t[o] = c->t[a];
+        c->step[o] = c->step[a];
+        c->dtc[o] = c->dtc[a];
+        c->dt_used[a] = 0.0;
+      }
+    }
+    return;
+  }
+  if (STAGE == 1 && tile == 0 && tid == 0) {
+    Ctrl* c = p.ctrl;
+    const int a = p.parity, o = 1 - p.parity;
+    c->t[o] = t_next;
+    c->step[o] = c->step[a] + 1;
+    c->dtc[o] = INF_BITS;
+    c->dt_used[a] = dt;
+    if (dt_cfl < 1e-12) atomicOr(&c->health, 2);
+  }
+
+  __shared__ Smem<R> sm;
+  const bool interior = i0 >= 2 && j0 >= 2 && i0 + TX + 2 <= p.nx && j0 + TY + 2 <= p.ny;
+  if (interior)
+    stage_body<R, STAGE, false>(p, sm, tile, i0, j0, t, dt, t_next);
+  else
+    stage_body<R, STAGE, true>(p, sm, tile, i0, j0, t, dt, t_next);
 }
 
 // ---------------------------------------------------------------------------------
