@@ -605,13 +605,12 @@ int dg2_get_timing(dg2_ctx* c, int64_t* steps, double* ms1, double* ms2) {
 int dg2_kernel_info(const dg2_ctx* c, int32_t* tile_x, int32_t* tile_y, int32_t* threads, int32_t* blocks,
                     int32_t* lds_bytes) {
   if (!c) return DG2_E_ARG;
-  const int rs = c->fp32 ? 4 : 8;
-  const int rb = (c->L.tx + 4) * (c->L.ty + 4), vb = (c->L.tx + 5) * (c->L.ty + 5);
   if (tile_x) *tile_x = c->L.tx;
   if (tile_y) *tile_y = c->L.ty;
   if (threads) *threads = c->L.threads;
   if (blocks) *blocks = c->L.grid;
-  if (lds_bytes) *lds_bytes = (12 * rb + vb) * rs + rb + (c->L.threads / 64) * 4 * 8;
+  if (lds_bytes)
+    *lds_bytes = c->fp32 ? (int32_t)sizeof(dg2k::Smem<float>) : (int32_t)sizeof(dg2k::Smem<double>);
   return DG2_OK;
 }
 

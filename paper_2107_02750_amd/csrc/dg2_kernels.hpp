@@ -33,9 +33,16 @@ namespace dg2k {
 #ifndef DG2_TILE32_Y
 #define DG2_TILE32_Y 8
 #endif
+#ifndef DG2_MINB64
+#define DG2_MINB64 1
+#endif
+#ifndef DG2_MINB32
+#define DG2_MINB32 1
+#endif
+// tile width and height, and the minimum resident blocks per CU the compiler must allow
 template <typename R> struct Tile;
-template <> struct Tile<double> { static constexpr int X = DG2_TILE64_X, Y = DG2_TILE64_Y; };
-template <> struct Tile<float> { static constexpr int X = DG2_TILE32_X, Y = DG2_TILE32_Y; };
+template <> struct Tile<double> { static constexpr int X = DG2_TILE64_X, Y = DG2_TILE64_Y, MINB = DG2_MINB64; };
+template <> struct Tile<float> { static constexpr int X = DG2_TILE32_X, Y = DG2_TILE32_Y, MINB = DG2_MINB32; };
 
 // LDS geometry of a tile: the cell box has a 2-cell halo, the vertex box one more
 template <typename R>
@@ -386,7 +393,8 @@ __device__ __forceinline__ double wave_min(double x) {
 // ---------------------------------------------------------------------------------
 template <typename R>
 struct Smem {
-  R c[9][Geo<R>::RB];   // halo box coefficients; later face states and fluxes
+  R c[6][Geo<R>::RB];   // planes 0-2: box means h0, qx0, qy0; later the face-side
+                        // states and then the face fluxes
   R zv[Geo<R>::VB];     // bed vertices of the box
   R z0[Geo<R>::RB];     // bed means of the box cells
   R um[Geo<R>::RB];     // mean velocities (zero at or below h_tol)
@@ -436,53 +444,92 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
   }
   auto zb = [&](int iv, int jv) -> R { return sm.zv[(jv - j0 + 2) * VX + (iv - i0 + 2)]; };
   const R dtr = R(dt);
-  for (int r = tid; r < RB; r += NT) {
-    const int a = r % RX, bb = r / RX;
-    const bool inx = a >= 2 && a < TX + 2, iny = bb >= 2 && bb < TY + 2;
-    const bool corner = (a == 1 || a == TX + 2) && (bb == 1 || bb == TY + 2);
-    if (!(inx || iny || corner)) continue;
+  const R* __restrict__ src = STAGE == 1 ? p.uin : p.ui;
+  // load box cell (a, bb), apply friction in stage 1 (npair: 0 centre only, 1 one Gauss
+  // pair whose slopes are picked by xdir, 2 both pairs, -1 none) and publish it
+  auto load_cell = [&](int a, int bb, int npair, bool xdir, R c[9]) {
+    const int r = bb * RX + a;
     int i = i0 - 2 + a, j = j0 - 2 + bb;
     if (EDGE) {
       i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
       j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
     }
     const unsigned k = (unsigned)(j * nx + i);
-    R c[9];
-    const R* __restrict__ src = STAGE == 1 ? p.uin : p.ui;
 #pragma unroll
     for (int q = 0; q < 9; ++q) c[q] = (src + q * n)[k];
-    if (STAGE == 1 && !corner) {
+    if (STAGE == 1 && npair >= 0) {
       const R nm = p.manning ? p.manning[k] : p.n_scalar;
       if (nm > R(0)) {
         const R gn2dt = p.g * nm * nm * dtr;
         R dx0, dy0;
         friction_inc(gn2dt, ht, c[0], c[3], c[6], dx0, dy0);
-        const bool needx = iny && a >= 1 && a <= TX + 2;
-        const bool needy = inx && bb >= 1 && bb <= TY + 2;
-        if (needx) {
+        if (npair == 2) {
+#pragma unroll
+          for (int d = 1; d <= 2; ++d) {
+            R dxp, dyp, dxm, dym;
+            friction_inc(gn2dt, ht, c[0] + c[d], c[3] + c[3 + d], c[6] + c[6 + d], dxp, dyp);
+            friction_inc(gn2dt, ht, c[0] - c[d], c[3] - c[3 + d], c[6] - c[6 + d], dxm, dym);
+            c[3 + d] += R(0.5) * (dxp - dxm);
+            c[6 + d] += R(0.5) * (dyp - dym);
+          }
+        } else if (npair == 1) {  // one pair; slopes selected, not indexed
+          const R h1 = xdir ? c[1] : c[2], qx1 = xdir ? c[4] : c[5], qy1 = xdir ? c[7] : c[8];
           R dxp, dyp, dxm, dym;
-          friction_inc(gn2dt, ht, c[0] + c[1], c[3] + c[4], c[6] + c[7], dxp, dyp);
-          friction_inc(gn2dt, ht, c[0] - c[1], c[3] - c[4], c[6] - c[7], dxm, dym);
-          c[4] += R(0.5) * (dxp - dxm);
-          c[7] += R(0.5) * (dyp - dym);
-        }
-        if (needy) {
-          R dxp, dyp, dxm, dym;
-          friction_inc(gn2dt, ht, c[0] + c[2], c[3] + c[5], c[6] + c[8], dxp, dyp);
-          friction_inc(gn2dt, ht, c[0] - c[2], c[3] - c[5], c[6] - c[8], dxm, dym);
-          c[5] += R(0.5) * (dxp - dxm);
-          c[8] += R(0.5) * (dyp - dym);
+          friction_inc(gn2dt, ht, c[0] + h1, c[3] + qx1, c[6] + qy1, dxp, dyp);
+          friction_inc(gn2dt, ht, c[0] - h1, c[3] - qx1, c[6] - qy1, dxm, dym);
+          const R ex = R(0.5) * (dxp - dxm), ey = R(0.5) * (dyp - dym);
+          c[4] += xdir ? ex : R(0);
+          c[5] += xdir ? R(0) : ex;
+          c[7] += xdir ? ey : R(0);
+          c[8] += xdir ? R(0) : ey;
         }
         c[3] += dx0;
         c[6] += dy0;
       }
     }
-#pragma unroll
-    for (int q = 0; q < 9; ++q) sm.c[q][r] = c[q];
+    sm.c[0][r] = c[0];  // means only: the slopes stay with the thread that owns the cell
+    sm.c[1][r] = c[3];
+    sm.c[2][r] = c[6];
     const bool wet = c[0] > ht;
     const R rh = frcp(fmaxr(c[0], Tiny<R>::v));
     sm.um[r] = wet ? c[3] * rh : R(0);
     sm.vm[r] = wet ? c[6] * rh : R(0);
+  };
+  // the own tile cell first (both Gauss pairs, the same path in every lane), then the
+  // halo: the first ring (one pair across the tile edge), the second ring (centre
+  // only) and the four first-ring corners (depth only)
+  R va[9], vb[9];  // the own cell and the thread's first-ring cell (ring items below)
+  load_cell(tid % TX + 2, tid / TX + 2, 2, true, va);
+  for (int h = tid; h < 2 * NRING + 4; h += NT) {
+    int a, bb, np;
+    bool xd;
+    if (h < NRING) {  // same numbering as the ring items below
+      if (h < TY) { a = 1; bb = h + 2; xd = true; }
+      else if (h < 2 * TY) { a = TX + 2; bb = h - TY + 2; xd = true; }
+      else if (h < 2 * TY + TX) { a = h - 2 * TY + 2; bb = 1; xd = false; }
+      else { a = h - 2 * TY - TX + 2; bb = TY + 2; xd = false; }
+      np = 1;
+    } else if (h < 2 * NRING) {
+      const int m = h - NRING;
+      if (m < TY) { a = 0; bb = m + 2; }
+      else if (m < 2 * TY) { a = TX + 3; bb = m - TY + 2; }
+      else if (m < 2 * TY + TX) { a = m - 2 * TY + 2; bb = 0; }
+      else { a = m - 2 * TY - TX + 2; bb = TY + 3; }
+      np = 0;
+      xd = true;
+    } else {
+      const int m = h - 2 * NRING;
+      a = (m & 1) ? TX + 2 : 1;
+      bb = (m & 2) ? TY + 2 : 1;
+      np = -1;
+      xd = true;
+    }
+    R tmp[9];
+    load_cell(a, bb, np, xd, tmp);
+    if (h < NRING) {  // first pass of this loop: h == tid, the thread's own ring item
+#pragma unroll
+      for (int q = 0; q < 9; ++q) vb[q] = tmp[q];
+    }
   }
   __syncthreads();
   for (int r = tid; r < RB; r += NT) {  // bed means of the box cells (eq 8, diagonal pairs)
@@ -513,8 +560,6 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
   const bool b_in = has_b && (!EDGE || (ri >= 0 && ri < nx && rj >= 0 && rj < ny));
 
   auto limit_cell = [&](int pos, int i, int j, int dirs, R v[9]) -> unsigned char {
-#pragma unroll
-    for (int q = 0; q < 9; ++q) v[q] = sm.c[q][pos];
     const R h0 = v[0];
     if (!(h0 > R(0))) {
 #pragma unroll
@@ -546,7 +591,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
         for (int var = 1; var <= 2; ++var) {
           const int q0 = 3 * var;
           const R a0 = v[q0];
-          const R am = sm.c[q0][pos - off], ap = sm.c[q0][pos + off];
+          const R am = sm.c[var][pos - off], ap = sm.c[var][pos + off];
           v[q0 + d] = minmod3(v[q0 + d], (ap - a0) * K<R>::inv_s3, (a0 - am) * K<R>::inv_s3);
         }
       }
@@ -559,15 +604,13 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
     return 0;
   };
 
-  R va[9];
   if (active) {  // a NaN anywhere in the cell's input would otherwise be absorbed
     R sum = R(0);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) sum += sm.c[q][cpos];
+    for (int q = 0; q < 9; ++q) sum += va[q];
     if (sum != sum) atomicOr(&p.ctrl->health, 1);
   }
   const unsigned char fa = limit_cell(cpos, active ? ci : i0, active ? cj : j0, 3, va);
-  R vb[9];
   unsigned char fb = 1;
   if (b_in) fb = limit_cell(rpos, ri, rj, rb_dir, vb);
   sm.flag[cpos] = fa;
@@ -855,12 +898,8 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
   }
 }
 
-#ifndef DG2_MIN_WAVES
-#define DG2_MIN_WAVES 1
-#endif
 template <typename R, int STAGE>
-__global__ __launch_bounds__(Geo<R>::NT) __attribute__((amdgpu_waves_per_eu(DG2_MIN_WAVES)))
-void stage_kernel(Params<R> p) {
+__global__ __launch_bounds__(Geo<R>::NT, Tile<R>::MINB) void stage_kernel(Params<R> p) {
   constexpr int TX = Geo<R>::TX, TY = Geo<R>::TY;
   const int b = blockIdx.x;
   const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
