@@ -133,6 +133,18 @@ __device__ __forceinline__ double fsqrt(double x) {
 }
 __device__ __forceinline__ float fsqrt(float x) { return x > 0.0f ? __builtin_sqrtf(x) : 0.0f; }
 
+// 1/sqrt(x) for x > 0: the hardware estimate and two Newton steps y <- y (3 - x y^2) / 2
+__device__ __forceinline__ double frsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double hy = 0.5 * y;
+  double e = __builtin_fma(-x * y, y, 1.0);
+  y = __builtin_fma(hy, e, y);
+  hy = 0.5 * y;
+  e = __builtin_fma(-x * y, y, 1.0);
+  return __builtin_fma(hy, e, y);
+}
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // y = h^(-1/3) for h > 0: a float log2/exp2 seed, then Newton on y^-3 = h,
 // y <- y (4 - h y^3) / 3, which doubles the correct bits each step
 __device__ __forceinline__ double finvcbrt(double h) {
@@ -276,7 +288,7 @@ __device__ __forceinline__ void friction_inc(R gn2dt, R ht, R h, R qx, R qy, R& 
   const R u = qx * y3, v = qy * y3;
   const R s2 = u * u + v * v;
   const bool act = wet && s2 > R(0);
-  const R rs = frcp(fsqrt(fmaxr(s2, Tiny<R>::v)));
+  const R rs = frsq(fmaxr(s2, Tiny<R>::v));  // 1/|u|
   const R w = gn2dt * (y3 * y);          // dt g n^2 h^(-4/3)
   const R a = w * u * u * rs, b = w * v * v * rs;
   const R ab = a + b;
@@ -623,6 +635,30 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
   Side<R> sw_, se_, ss_, sn_;
   const R slack = R(dsqrt(p.gd * p.htd));
   auto zside = [&](int pos, R zf) -> R { return sm.flag[pos] ? sm.z0[pos] : zf; };
+  // ring item: W ring publishes its east side, S ring its north side; E and N ring
+  // cells keep their west / south side for the tile's east / north faces
+  Side<R> sb_;
+  sb_.h = sb_.u = sb_.v = sb_.z = R(0);
+  if (b_in) {
+    const int oa = rb_side == 0 ? 1 : (rb_side == 1 ? -1 : 0);
+    const int ob = rb_side == 2 ? 1 : (rb_side == 3 ? -1 : 0);
+    const int npos = rpos + oa + ob * RX;  // the tile cell across the face
+    const int ni = ri + oa, nj = rj + ob;
+    R zf;
+    if (rb_side == 0) zf = R(0.5) * (zb(ri + 1, rj + 1) + zb(ri + 1, rj));
+    else if (rb_side == 1) zf = R(0.5) * (zb(ri, rj + 1) + zb(ri, rj));
+    else if (rb_side == 2) zf = R(0.5) * (zb(ri, rj + 1) + zb(ri + 1, rj + 1));
+    else zf = R(0.5) * (zb(ri, rj) + zb(ri + 1, rj));
+    const R own = fb ? sm.z0[rpos] : zf;
+    const R nb = (!EDGE || (ni >= 0 && ni < nx && nj >= 0 && nj < ny)) ? zside(npos, zf) : own;
+    const R zs = fmaxr(own, nb);
+    const bool dx_ = rb_dir == 1;  // select, not index: keeps vb in registers
+    const R h1 = dx_ ? vb[1] : vb[2], qx1 = dx_ ? vb[4] : vb[5], qy1 = dx_ ? vb[7] : vb[8];
+    const R sg = (rb_side == 0 || rb_side == 2) ? s3 : -s3;  // toward the tile
+    sb_ = revise(vb[0] + sg * h1, vb[3] + sg * qx1, vb[6] + sg * qy1, own, zs, ht);
+    sb_.u = vcap(sb_.u, sm.um[rpos], sm.um[npos], slack);
+    sb_.v = vcap(sb_.v, sm.vm[rpos], sm.vm[npos], slack);
+  }
   if (active) {
     const R zW = R(0.5) * (zb(ci, cj + 1) + zb(ci, cj));
     const R zE = R(0.5) * (zb(ci + 1, cj + 1) + zb(ci + 1, cj));
@@ -651,29 +687,43 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
     ss_.u = vcap(ss_.u, u0, sm.um[ps], slack); ss_.v = vcap(ss_.v, v0, sm.vm[ps], slack);
     sn_.u = vcap(sn_.u, u0, sm.um[pn], slack); sn_.v = vcap(sn_.v, v0, sm.vm[pn], slack);
   }
-  // ring item: W ring publishes its east side, S ring its north side; E and N ring
-  // cells keep their west / south side for the tile's east / north faces
-  Side<R> sb_;
-  sb_.h = sb_.u = sb_.v = sb_.z = R(0);
-  if (b_in) {
-    const int oa = rb_side == 0 ? 1 : (rb_side == 1 ? -1 : 0);
-    const int ob = rb_side == 2 ? 1 : (rb_side == 3 ? -1 : 0);
-    const int npos = rpos + oa + ob * RX;  // the tile cell across the face
-    const int ni = ri + oa, nj = rj + ob;
-    R zf;
-    if (rb_side == 0) zf = R(0.5) * (zb(ri + 1, rj + 1) + zb(ri + 1, rj));
-    else if (rb_side == 1) zf = R(0.5) * (zb(ri, rj + 1) + zb(ri, rj));
-    else if (rb_side == 2) zf = R(0.5) * (zb(ri, rj + 1) + zb(ri + 1, rj + 1));
-    else zf = R(0.5) * (zb(ri, rj) + zb(ri + 1, rj));
-    const R own = fb ? sm.z0[rpos] : zf;
-    const R nb = (!EDGE || (ni >= 0 && ni < nx && nj >= 0 && nj < ny)) ? zside(npos, zf) : own;
-    const R zs = fmaxr(own, nb);
-    const bool dx_ = rb_dir == 1;  // select, not index: keeps vb in registers
-    const R h1 = dx_ ? vb[1] : vb[2], qx1 = dx_ ? vb[4] : vb[5], qy1 = dx_ ? vb[7] : vb[8];
-    const R sg = (rb_side == 0 || rb_side == 2) ? s3 : -s3;  // toward the tile
-    sb_ = revise(vb[0] + sg * h1, vb[3] + sg * qx1, vb[6] + sg * qy1, own, zs, ht);
-    sb_.u = vcap(sb_.u, sm.um[rpos], sm.um[npos], slack);
-    sb_.v = vcap(sb_.v, sm.vm[rpos], sm.vm[npos], slack);
+  // the parts of L that need only the cell's own face sides (2-point Gauss fluxes and
+  // bed source), taken now so that the sides need not stay live past the face phase:
+  // gx/gy: F(U+) + F(U-) per direction; sx/sy: the source terms of L0 and L1
+  R gx[3] = {R(0), R(0), R(0)}, gy[3] = {R(0), R(0), R(0)};
+  R sx0 = R(0), sx1 = R(0), sy0 = R(0), sy1 = R(0);
+  const R g = p.g;
+  if (active) {
+    const R k2s3 = R(2) * s3 * g * (R(1) / p.dx);
+    {  // x direction
+      const R hb0 = R(0.5) * (se_.h + sw_.h), hb1 = (se_.h - sw_.h) * K<R>::inv_2s3;
+      const R qxE = se_.h * se_.u, qxW = sw_.h * sw_.u, qyE = se_.h * se_.v, qyW = sw_.h * sw_.v;
+      const R qb0 = R(0.5) * (qxE + qxW), qb1 = (qxE - qxW) * K<R>::inv_2s3;
+      const R rb0 = R(0.5) * (qyE + qyW), rb1 = (qyE - qyW) * K<R>::inv_2s3;
+      const R zb1 = (se_.z - sw_.z) * K<R>::inv_2s3;
+      R Fp[3], Fm[3];
+      gauss_flux(g, ht, hb0 + hb1, qb0 + qb1, rb0 + rb1, Fp);
+      gauss_flux(g, ht, hb0 - hb1, qb0 - qb1, rb0 - rb1, Fm);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) gx[q] = Fp[q] + Fm[q];
+      sx0 = k2s3 * hb0 * zb1;
+      sx1 = k2s3 * hb1 * zb1;
+    }
+    {  // y direction: Gp/Gm are [mass, y-mom (normal), x-mom (tangential)]
+      const R hb0 = R(0.5) * (sn_.h + ss_.h), hb1 = (sn_.h - ss_.h) * K<R>::inv_2s3;
+      const R qxN = sn_.h * sn_.u, qxS = ss_.h * ss_.u, qyN = sn_.h * sn_.v, qyS = ss_.h * ss_.v;
+      const R qb0 = R(0.5) * (qxN + qxS), qb1 = (qxN - qxS) * K<R>::inv_2s3;
+      const R rb0 = R(0.5) * (qyN + qyS), rb1 = (qyN - qyS) * K<R>::inv_2s3;
+      const R zb1 = (sn_.z - ss_.z) * K<R>::inv_2s3;
+      R Gp[3], Gm[3];
+      gauss_flux(g, ht, hb0 + hb1, rb0 + rb1, qb0 + qb1, Gp);
+      gauss_flux(g, ht, hb0 - hb1, rb0 - rb1, qb0 - qb1, Gm);
+      gy[0] = Gp[0] + Gm[0];
+      gy[1] = Gp[2] + Gm[2];  // x-momentum
+      gy[2] = Gp[1] + Gm[1];  // y-momentum
+      sy0 = k2s3 * hb0 * zb1;
+      sy1 = k2s3 * hb1 * zb1;
+    }
   }
   if (active) {  // s_c is no longer read: it now holds face data
     s_side[0 * RB + cpos] = se_.h;
@@ -697,7 +747,6 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
 
   // ---- phase 2c: HLL on the west and south face of each position ----
   const double t_stage = STAGE == 1 ? t : t_next;
-  const R g = p.g;
   double led_in = 0.0, led_out = 0.0, led_clip = 0.0;
   const double wflux = 0.5 * dt * p.dxd;  // ledger weight: RK2 half step times face width
   R fw[3] = {R(0), R(0), R(0)}, fs[3] = {R(0), R(0), R(0)};
@@ -784,42 +833,17 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
     const R fe[3] = {s_side[0 * RB + cpos + 1], s_side[1 * RB + cpos + 1], s_side[2 * RB + cpos + 1]};
     const R fn[3] = {s_side[3 * RB + cpos + RX], s_side[4 * RB + cpos + RX], s_side[5 * RB + cpos + RX]};
     const R idx = R(1) / p.dx;
-    const R k2s3 = R(2) * s3 * g * idx;
+    const R c = -s3 * idx;
     R L[9];
-    {  // x direction
-      const R hb0 = R(0.5) * (se_.h + sw_.h), hb1 = (se_.h - sw_.h) * K<R>::inv_2s3;
-      const R qxE = se_.h * se_.u, qxW = sw_.h * sw_.u, qyE = se_.h * se_.v, qyW = sw_.h * sw_.v;
-      const R qb0 = R(0.5) * (qxE + qxW), qb1 = (qxE - qxW) * K<R>::inv_2s3;
-      const R rb0 = R(0.5) * (qyE + qyW), rb1 = (qyE - qyW) * K<R>::inv_2s3;
-      const R zb1 = (se_.z - sw_.z) * K<R>::inv_2s3;
-      R Fp[3], Fm[3];
-      gauss_flux(g, ht, hb0 + hb1, qb0 + qb1, rb0 + rb1, Fp);
-      gauss_flux(g, ht, hb0 - hb1, qb0 - qb1, rb0 - rb1, Fm);
-      L[0] = -(fe[0] - fw[0]) * idx;
-      L[3] = -(fe[1] - fw[1]) * idx - k2s3 * hb0 * zb1;
-      L[6] = -(fe[2] - fw[2]) * idx;
-      const R c = -s3 * idx;
-      L[1] = c * (fe[0] + fw[0] - Fp[0] - Fm[0]);
-      L[4] = c * (fe[1] + fw[1] - Fp[1] - Fm[1]) - k2s3 * hb1 * zb1;
-      L[7] = c * (fe[2] + fw[2] - Fp[2] - Fm[2]);
-    }
-    {  // y direction
-      const R hb0 = R(0.5) * (sn_.h + ss_.h), hb1 = (sn_.h - ss_.h) * K<R>::inv_2s3;
-      const R qxN = sn_.h * sn_.u, qxS = ss_.h * ss_.u, qyN = sn_.h * sn_.v, qyS = ss_.h * ss_.v;
-      const R qb0 = R(0.5) * (qxN + qxS), qb1 = (qxN - qxS) * K<R>::inv_2s3;
-      const R rb0 = R(0.5) * (qyN + qyS), rb1 = (qyN - qyS) * K<R>::inv_2s3;
-      const R zb1 = (sn_.z - ss_.z) * K<R>::inv_2s3;
-      R Gp[3], Gm[3];  // [mass, y-mom (normal), x-mom (tangential)]
-      gauss_flux(g, ht, hb0 + hb1, rb0 + rb1, qb0 + qb1, Gp);
-      gauss_flux(g, ht, hb0 - hb1, rb0 - rb1, qb0 - qb1, Gm);
-      L[0] += -(fn[0] - fs[0]) * idx;
-      L[3] += -(fn[1] - fs[1]) * idx;
-      L[6] += -(fn[2] - fs[2]) * idx - k2s3 * hb0 * zb1;
-      const R c = -s3 * idx;
-      L[2] = c * (fn[0] + fs[0] - Gp[0] - Gm[0]);
-      L[5] = c * (fn[1] + fs[1] - Gp[2] - Gm[2]);
-      L[8] = c * (fn[2] + fs[2] - Gp[1] - Gm[1]) - k2s3 * hb1 * zb1;
-    }
+    L[0] = -(fe[0] - fw[0]) * idx + -(fn[0] - fs[0]) * idx;
+    L[3] = (-(fe[1] - fw[1]) * idx - sx0) + -(fn[1] - fs[1]) * idx;
+    L[6] = -(fe[2] - fw[2]) * idx + (-(fn[2] - fs[2]) * idx - sy0);
+    L[1] = c * (fe[0] + fw[0] - gx[0]);
+    L[4] = c * (fe[1] + fw[1] - gx[1]) - sx1;
+    L[7] = c * (fe[2] + fw[2] - gx[2]);
+    L[2] = c * (fn[0] + fs[0] - gy[0]);
+    L[5] = c * (fn[1] + fs[1] - gy[1]);
+    L[8] = c * (fn[2] + fs[2] - gy[2]) - sy1;
     R u[9];
     if (STAGE == 1) {
 #pragma unroll
