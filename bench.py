@@ -9,9 +9,11 @@ timed region starts; K steps are timed between device synchronisations.
 
 Also reported, on the same line: the FP32 instantiation on the same workload with its
 depth error against the FP64 path, the same terrain as configured (dry start, channel
-inflow hydrograph) timed from a snapshot at t = 3600 s, the stage-kernel durations from
-HIP events recorded on the launch stream with the roofline of the dominant kernel, and
-the FP64 CPU oracle timed on this host's cores on a bounded sample.
+inflow hydrograph) timed from a snapshot at t = 3600 s, the urban precision run (FP32
+with per-tile bed datums against FP64: depth error, mass drift, also with the bed raised
+by 1000 m), the stage-kernel durations from HIP events recorded on the launch stream
+with the roofline of the dominant kernel, and the FP64 CPU oracle timed on this host's
+cores on a bounded sample.
 """
 import argparse
 import json
@@ -97,6 +99,44 @@ def cpu_baseline(sc, budget_s):
                        f"workload ({secs:.1f} s)")
 
 
+def precision_form(dg2, S, n, t_end):
+    """The urban terrain (flat ground with building blocks, dry start, 1 m deep inflow at
+    2 m/s along the west edge) run to t_end in FP64 and in FP32, with the bed stored
+    relative to per-tile datums and stored absolute, at its own elevation and raised by
+    1000 m: the FP32 depth error against the FP64 run, the mass-balance drift of each
+    run, and the cell-update rate."""
+    import torch
+    sc = S.urban_blocks(n=n)
+    res = {"workload": f"urban blocks {n}x{n}, dx=2 m, 4000 blocks, 1 m at 2 m/s inflow on W, "
+                       "n=0.02, dry start", "cells": n * n, "t_end": t_end}
+
+    def one(s, prec, datum):
+        sim = dg2.DG2(s, prec, bed_datum=datum)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = sim.run(t_end)
+        el = time.perf_counter() - t0
+        sc_ = sim.scalars()
+        bal = sc_["mass"] - sc_["mass_in"] + sc_["mass_out"] - sc_["mass_clip"]  # M0 = 0
+        r = {"value": n * n * steps / el, "unit": "cell-updates/s", "steps": steps,
+             "mass_balance_rel": bal / max(sc_["mass"], sc_["mass_in"]),
+             "bed_quantum_m": sim.bed_info()["quantum"]}
+        return sim.read(0).astype(np.float64), r
+
+    h64, res["fp64"] = one(sc, dg2.FP64, False)
+    hi = sc.replace(zv=sc.zv + 1000.0)
+    for key, s, datum in (("fp32_datum", sc, True), ("fp32_absolute", sc, False),
+                          ("fp32_datum_bed_plus_1000m", hi, True),
+                          ("fp32_absolute_bed_plus_1000m", hi, False)):
+        h, r = one(s, dg2.FP32, datum)
+        d = h - h64
+        r["max_depth_error_m"] = float(np.abs(d).max())
+        r["rms_depth_error_m"] = float(np.sqrt(np.mean(d * d)))
+        res[key] = r
+    res["error_vs"] = "the FP64 GPU run on the same bed (which matches the FP64 oracle to 1e-12)"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +144,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=1024, help="grid side (default: the 1024 case)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--n-urban", type=int, default=2048, help="grid side of the urban precision run")
+    ap.add_argument("--t-urban", type=float, default=600.0, help="simulated seconds of the urban run")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the FP64 timed region (for profiler runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -199,6 +241,12 @@ def main():
                                 "spin_up_steps": spin, "spin_up_s": spin_s}
         print(f"[bench] as configured {out['as_configured']['value']:.4g} cell-updates/s, "
               f"wet {wet:.4f}", file=sys.stderr, flush=True)
+        out["precision_form"] = precision_form(dg2, S, args.n_urban, args.t_urban)
+        pf = out["precision_form"]
+        print(f"[bench] urban {pf['cells']} cells to t={pf['t_end']:.0f} s: FP32 datum max depth err "
+              f"{pf['fp32_datum']['max_depth_error_m']:.3g} m (bed +1000 m: "
+              f"{pf['fp32_datum_bed_plus_1000m']['max_depth_error_m']:.3g} m; absolute FP32 there: "
+              f"{pf['fp32_absolute_bed_plus_1000m']['max_depth_error_m']:.3g} m)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
         print(f"[bench] CPU oracle {out['cpu_baseline']['value']:.4g} cell-updates/s on "
               f"{out['cpu_baseline']['cores']} threads", file=sys.stderr, flush=True)

@@ -24,6 +24,18 @@
  *  - Precision: DG2_FP64 computes and stores everything in double; DG2_FP32 computes
  *    and stores the coefficients and the bed in float, while time, the time step and
  *    the mass ledger stay in double. "real" below is the context's precision.
+ *  - Bed datum (DG2_FP32 with bed_datum = 1): each tile of the stage kernels gets a
+ *    datum, a whole number of metres near the middle of the bed range around the tile,
+ *    and the bed is stored in float relative to the datum of the tile that owns each
+ *    vertex, rounded to a power-of-two quantum (dg2_bed_info) chosen so that every
+ *    elevation a tile sees in its own frame, and every mean and difference of them
+ *    the scheme forms, is exact in float. The FP32 arithmetic uses the bed only
+ *    through such differences, so a tile's results do not depend on its datum, the
+ *    two tiles that share a face compute the same flux, and raising the whole bed
+ *    (and any still-water level) by a whole number of metres leaves every result
+ *    unchanged. Depth precision is then set by the local relief, not by the absolute
+ *    elevation. The quantum is the bed's only change (at most half a quantum per
+ *    vertex).
  *  - Memory: the caller owns every input; host inputs are copied during dg2_init and
  *    may be freed afterwards. The caller allocates the device workspace (its size from
  *    dg2_workspace_size) and keeps it alive, untouched, until dg2_destroy. The library
@@ -85,6 +97,9 @@ typedef struct {
   int32_t precision;       /* DG2_FP64 or DG2_FP32 */
   int32_t limiter;         /* 1: minmod on eta, qx, qy; 0: off (fronts stay first order) */
   int32_t edge_kind[4];    /* default kind of each edge W, E, S, N: transmissive or wall */
+  int32_t bed_datum;       /* DG2_FP32 only (ignored for FP64): 1 stores the bed relative
+                              to a per-tile datum, 0 stores absolute elevations; see
+                              dg2_bed_info */
 } dg2_config;
 
 typedef struct {
@@ -168,6 +183,27 @@ int dg2_get_timing(dg2_ctx *c, int64_t *steps, double *ms_stage1, double *ms_sta
  * height in cells, threads per block, blocks per launch, LDS bytes per block. */
 int dg2_kernel_info(const dg2_ctx *c, int32_t *tile_x, int32_t *tile_y, int32_t *threads,
                     int32_t *blocks, int32_t *lds_bytes);
+
+/* The bed representation of a context: the quantum (m) the stored bed was rounded to
+ * (0 when the bed is stored unrounded: FP64, or FP32 without a datum) and the largest
+ * |z - datum| over the vertices any tile reads (the absolute elevation when there is
+ * no datum). */
+int dg2_bed_info(const dg2_ctx *c, double *quantum, double *max_local);
+
+/* Host-only (no device needed): the per-tile datums and the stored bed that dg2_init
+ * builds for an FP32 configuration with bed_datum = 1. zv: (nx+1)*(ny+1) vertex bed
+ * (host). zrel (host, (nx+1)*(ny+1) doubles, may be NULL): the stored bed, relative to
+ * the datum of each vertex's owner tile (the tile of cell (min(i, nx-1),
+ * min(j, ny-1))) and rounded to the quantum; every value is a float. datum (host,
+ * n_tiles doubles, may be NULL): tile (ti, tj) at tj*tiles_x + ti, tiles as reported
+ * by dg2_tile_grid. DG2_E_UNSUPPORTED if the relief around some tile reaches 2^20 m. */
+int dg2_plan_bed_datum(const dg2_config *cfg, const double *zv, double *zrel, double *datum,
+                       double *quantum, double *max_local);
+
+/* Host-only: the tile grid of the stage kernels for a configuration (tile width and
+ * height in cells, tiles along x and y). */
+int dg2_tile_grid(const dg2_config *cfg, int32_t *tile_x, int32_t *tile_y, int32_t *tiles_x,
+                  int32_t *tiles_y);
 
 const char *dg2_last_error(const dg2_ctx *c);
 const char *dg2_init_error(void);

@@ -24,7 +24,7 @@ constexpr size_t ALIGN = 256;
 size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t u0, u1, ui, zv, man, bface, segs, knots, ctrl, ledger, scal, total;
+  size_t u0, u1, ui, zv, datum, man, bface, segs, knots, ctrl, ledger, scal, total;
   int tx, ty, threads, tiles_x, tiles_y, n_tiles, per_xcd, grid;
 };
 
@@ -50,6 +50,7 @@ Layout layout(const dg2_config& c) {
   L.u1 = take(9 * n * rs);
   L.ui = take(9 * n * rs);
   L.zv = take((size_t)(c.nx + 1) * (c.ny + 1) * rs);
+  L.datum = take((size_t)L.n_tiles * rs);
   L.man = take(n * rs);
   L.bface = take((size_t)2 * (c.nx + c.ny) * sizeof(int));
   L.segs = take(DG2_MAX_SEGMENTS * sizeof(Seg));
@@ -72,6 +73,9 @@ struct dg2_ctx {
   char* ws;
   size_t n;
   bool fp32;
+  bool datum;          // FP32 bed stored relative to per-tile datums
+  double bed_q;        // quantum of the stored bed (0: unrounded)
+  double bed_max;      // largest |z - datum| a tile reads (absolute |z| without datums)
   bool has_manning;
   double manning_scalar;
   int nsegs;
@@ -112,6 +116,7 @@ Params<R> params(const dg2_ctx* c) {
   p.vbuf = reinterpret_cast<R*>(c->ws + (c->parity ? L.u0 : L.u1));
   p.ui = reinterpret_cast<R*>(c->ws + L.ui);
   p.zv = reinterpret_cast<const R*>(c->ws + L.zv);
+  p.datum = c->datum ? reinterpret_cast<const R*>(c->ws + L.datum) : nullptr;
   p.manning = c->has_manning ? reinterpret_cast<const R*>(c->ws + L.man) : nullptr;
   p.bface = reinterpret_cast<const int*>(c->ws + L.bface);
   p.segs = reinterpret_cast<const Seg*>(c->ws + L.segs);
@@ -212,7 +217,50 @@ int check_config(const dg2_config* cfg) {
   if (cfg->nx < 1 || cfg->ny < 1) return DG2_E_ARG;
   if ((long long)cfg->nx * cfg->ny > (1LL << 31)) return DG2_E_UNSUPPORTED;
   if (cfg->precision != DG2_FP64 && cfg->precision != DG2_FP32) return DG2_E_ARG;
+  if (cfg->bed_datum != 0 && cfg->bed_datum != 1) return DG2_E_ARG;
   return DG2_OK;
+}
+
+// Per-tile datums and the quantised relative bed (FP32 with a bed datum). Each tile's
+// datum is the whole number of metres nearest the middle of the bed range over the
+// vertices its stage kernels read (the tile's vertices and a 2-cell halo). With B the
+// largest |z - datum| over those reads, the bed is rounded to the quantum
+// q = 2^-(20 - ceil(log2 B)), so |z| / q <= 2^20 in every tile's frame: the shifts
+// between frames (whole metres, multiples of q), the face means (q/2), the cell means
+// (q/4) and the differences of any two of them stay below 2^24 units of their
+// quantum, i.e. exact in float.
+bool plan_datum(const dg2_config& cfg, const Layout& L, const double* zv, std::vector<double>& zrel,
+                std::vector<double>& datum, double& q, double& bmax) {
+  const int nx = cfg.nx, ny = cfg.ny, tx = L.tx, ty = L.ty;
+  const size_t w = (size_t)nx + 1;
+  datum.assign(L.n_tiles, 0.0);
+  bmax = 0.0;
+  for (int tj = 0; tj < L.tiles_y; ++tj)
+    for (int ti = 0; ti < L.tiles_x; ++ti) {
+      const int a0 = std::max(ti * tx - 2, 0), a1 = std::min(ti * tx + tx + 2, nx);
+      const int b0 = std::max(tj * ty - 2, 0), b1 = std::min(tj * ty + ty + 2, ny);
+      double lo = INFINITY, hi = -INFINITY;
+      for (int jv = b0; jv <= b1; ++jv)
+        for (int iv = a0; iv <= a1; ++iv) {
+          const double z = zv[jv * w + iv];
+          lo = std::min(lo, z);
+          hi = std::max(hi, z);
+        }
+      const double d = std::floor(0.5 * (lo + hi) + 0.5);
+      datum[(size_t)tj * L.tiles_x + ti] = d;
+      bmax = std::max(bmax, std::max(hi - d, d - lo));
+    }
+  if (!(bmax < 1048576.0)) return false;  // relief beyond 2^20 m: no useful quantum
+  const int e = bmax > 0x1p-20 ? (int)std::ceil(std::log2(bmax)) : -20;
+  q = std::ldexp(1.0, e - 20);
+  zrel.resize(w * (ny + 1));
+  for (int jv = 0; jv <= ny; ++jv)
+    for (int iv = 0; iv <= nx; ++iv) {
+      const int oi = std::min(iv, nx - 1), oj = std::min(jv, ny - 1);
+      const double d = datum[(size_t)(oj / ty) * L.tiles_x + oi / tx];
+      zrel[jv * w + iv] = q * std::nearbyint((zv[jv * w + iv] - d) / q);
+    }
+  return true;
 }
 
 template <typename R>
@@ -237,7 +285,20 @@ int init_device(dg2_ctx* c, const double* zv, const double* man, int mode, const
     return DG2_OK;
   };
   do {
-    if ((rc = conv(zv, nv, c->L.zv))) break;
+    if (c->datum) {
+      std::vector<double> zrel, datum;
+      if (!plan_datum(c->cfg, c->L, zv, zrel, datum, c->bed_q, c->bed_max)) {
+        rc = fail(c, DG2_E_UNSUPPORTED, "bed relief too large for a float datum");
+        break;
+      }
+      if ((rc = conv(zrel.data(), nv, c->L.zv))) break;
+      if ((rc = conv(datum.data(), datum.size(), c->L.datum))) break;
+    } else {
+      c->bed_q = 0.0;
+      c->bed_max = 0.0;
+      for (size_t k = 0; k < nv; ++k) c->bed_max = std::max(c->bed_max, std::fabs(zv[k]));
+      if ((rc = conv(zv, nv, c->L.zv))) break;
+    }
     if (man && (rc = conv(man, n, c->L.man))) break;
     if (mode != DG2_INIT_LEVEL) {
       size_t cnt = mode == DG2_INIT_PLANES ? 9 * n : (mode == DG2_INIT_MEANS ? 3 * n : 3 * nv);
@@ -370,6 +431,7 @@ int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, dou
   x->ws = reinterpret_cast<char*>(d_workspace);
   x->n = n;
   x->fp32 = c.precision == DG2_FP32;
+  x->datum = x->fp32 && c.bed_datum == 1;
   x->has_manning = manning != nullptr;
   x->manning_scalar = manning_scalar;
   x->nsegs = n_bcs;
@@ -611,6 +673,41 @@ int dg2_kernel_info(const dg2_ctx* c, int32_t* tile_x, int32_t* tile_y, int32_t*
   if (blocks) *blocks = c->L.grid;
   if (lds_bytes)
     *lds_bytes = c->fp32 ? (int32_t)sizeof(dg2k::Smem<float>) : (int32_t)sizeof(dg2k::Smem<double>);
+  return DG2_OK;
+}
+
+int dg2_plan_bed_datum(const dg2_config* cfg, const double* zv, double* zrel, double* datum,
+                       double* quantum, double* max_local) {
+  const int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!zv) return DG2_E_ARG;
+  const Layout L = layout(*cfg);
+  std::vector<double> zr, d;
+  double q = 0.0, b = 0.0;
+  if (!plan_datum(*cfg, L, zv, zr, d, q, b)) return DG2_E_UNSUPPORTED;
+  if (zrel) std::memcpy(zrel, zr.data(), zr.size() * sizeof(double));
+  if (datum) std::memcpy(datum, d.data(), d.size() * sizeof(double));
+  if (quantum) *quantum = q;
+  if (max_local) *max_local = b;
+  return DG2_OK;
+}
+
+int dg2_tile_grid(const dg2_config* cfg, int32_t* tile_x, int32_t* tile_y, int32_t* tiles_x,
+                  int32_t* tiles_y) {
+  const int rc = check_config(cfg);
+  if (rc) return rc;
+  const Layout L = layout(*cfg);
+  if (tile_x) *tile_x = L.tx;
+  if (tile_y) *tile_y = L.ty;
+  if (tiles_x) *tiles_x = L.tiles_x;
+  if (tiles_y) *tiles_y = L.tiles_y;
+  return DG2_OK;
+}
+
+int dg2_bed_info(const dg2_ctx* c, double* quantum, double* max_local) {
+  if (!c) return DG2_E_ARG;
+  if (quantum) *quantum = c->bed_q;
+  if (max_local) *max_local = c->bed_max;
   return DG2_OK;
 }
 

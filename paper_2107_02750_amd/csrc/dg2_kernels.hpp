@@ -80,7 +80,8 @@ struct Params {
   const R* __restrict__ uin;   // U^n (the stage-1 input; stage 2 reads ui)
   R* __restrict__ vbuf;        // V^n out (stage 1); V^n in, U^{n+1} out (stage 2)
   R* __restrict__ ui;          // U^int out (stage 1)
-  const R* __restrict__ zv;    // vertex bed
+  const R* __restrict__ zv;    // vertex bed (relative to the owner tile's datum if datum)
+  const R* __restrict__ datum; // per tile, whole metres (FP32 with a bed datum), or nullptr
   const R* __restrict__ manning;  // per cell, or nullptr
   const int* __restrict__ bface;  // boundary faces: W[ny], E[ny], S[nx], N[nx]
   const Seg* __restrict__ segs;
@@ -216,25 +217,36 @@ __device__ __forceinline__ void step_time(const Params<R>& p, double& t, double&
   dt = d;
 }
 
-// a face side after the wet/dry revision: depth, velocities, revised bed
+// a face side after the wet/dry revision: depth, velocities, and the revised bed
+// z** = z + m (FP64: z = z**, m = 0; FP32: z = z*, m = min(h + zb - z*, 0))
 template <typename R>
 struct Side {
-  R h, u, v, z;
+  R h, u, v, z, m;
 };
 
 // revision of one side's limit (h, qx, qy) with this side's bed zb and the face's
 // z* = zs: h* = max(0, eta - z*), velocities from the unrevised depth (zero at or
-// below h_tol), z** = min(z*, eta)
+// below h_tol), z** = min(z*, eta). FP32 forms the same quantities from the bed
+// difference zb - z* (exact there), never from an absolute eta, so that they do not
+// depend on the elevation datum.
 template <typename R>
 __device__ __forceinline__ Side<R> revise(R h, R qx, R qy, R zb, R zs, R ht) {
   Side<R> s;
-  const R eta = h + zb;
-  s.h = fmax0(eta - zs);
+  if constexpr (sizeof(R) == 8) {
+    const R eta = h + zb;
+    s.h = fmax0(eta - zs);
+    s.z = fminr(eta, zs);
+    s.m = R(0);
+  } else {
+    const R d = h + (zb - zs);
+    s.h = fmax0(d);
+    s.z = zs;
+    s.m = fminr(d, R(0));
+  }
   const bool wet = h > ht;
   const R r = frcp(fmaxr(h, Tiny<R>::v));
   s.u = wet ? qx * r : R(0);
   s.v = wet ? qy * r : R(0);
-  s.z = fminr(eta, zs);
   return s;
 }
 
@@ -298,16 +310,33 @@ __device__ __forceinline__ void friction_inc(R gn2dt, R ht, R h, R qx, R qy, R& 
   dqy = act ? -qy * ab * d1 * inv : R(0);
 }
 
+// datum of the tile holding cell (i, j) (0 without a datum)
 template <typename R>
-__device__ __forceinline__ R zvat(const Params<R>& p, int iv, int jv) {
-  return p.zv[(long long)jv * (p.nx + 1) + iv];
+__device__ __forceinline__ R tile_datum(const Params<R>& p, int i, int j) {
+  if constexpr (sizeof(R) == 8) return R(0);  // FP64 stores absolute elevations
+  return p.datum ? p.datum[(j / Geo<R>::TY) * p.tiles_x + i / Geo<R>::TX] : R(0);
 }
 
-// bed mean and slopes of cell (i, j) (eq 8; mean summed in diagonal pairs)
+// bed at vertex (iv, jv) in the frame of datum dT: the stored value is relative to the
+// datum of the tile owning the vertex (the tile of cell (min(iv, nx-1), min(jv, ny-1)));
+// datums are whole metres and the stored bed is quantised, so the shift is exact
+template <typename R>
+__device__ __forceinline__ R zvat(const Params<R>& p, int iv, int jv, R dT) {
+  R z = p.zv[(long long)jv * (p.nx + 1) + iv];
+  if (sizeof(R) == 4 && p.datum) {
+    const int oi = iv < p.nx ? iv : p.nx - 1, oj = jv < p.ny ? jv : p.ny - 1;
+    z += tile_datum(p, oi, oj) - dT;
+  }
+  return z;
+}
+
+// bed mean and slopes of cell (i, j) (eq 8; mean summed in diagonal pairs), in the frame
+// of the cell's tile datum
 template <typename R>
 __device__ __forceinline__ void bed(const Params<R>& p, int i, int j, R& z0, R& z1x, R& z1y) {
-  const R sw = zvat(p, i, j), se = zvat(p, i + 1, j);
-  const R nw = zvat(p, i, j + 1), ne = zvat(p, i + 1, j + 1);
+  const R dT = tile_datum(p, i, j);
+  const R sw = zvat(p, i, j, dT), se = zvat(p, i + 1, j, dT);
+  const R nw = zvat(p, i, j + 1, dT), ne = zvat(p, i + 1, j + 1, dT);
   z0 = R(0.25) * ((ne + sw) + (nw + se));
   z1x = (R(0.5) * (ne + se) - R(0.5) * (nw + sw)) * K<R>::inv_2s3;
   z1y = (R(0.5) * (nw + ne) - R(0.5) * (sw + se)) * K<R>::inv_2s3;
@@ -444,6 +473,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
   }
 
   // ---- phase 1: the box (friction applied in stage 1) and its bed vertices ----
+  const R dT = (sizeof(R) == 4 && p.datum) ? p.datum[tile] : R(0);
   // vertex (iv, jv) sits at box position (iv - i0 + 2, jv - j0 + 2); a clamped halo
   // cell only uses vertices of in-domain cells, which lie in the box
   for (int r = tid; r < VB; r += NT) {
@@ -452,7 +482,12 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
       iv = iv < 0 ? 0 : (iv > nx ? nx : iv);
       jv = jv < 0 ? 0 : (jv > ny ? ny : jv);
     }
-    sm.zv[r] = p.zv[(unsigned)(jv * (nx + 1) + iv)];
+    R z = p.zv[(unsigned)(jv * (nx + 1) + iv)];
+    if (sizeof(R) == 4 && p.datum) {  // to this tile's frame
+      const int oi = iv < nx ? iv : nx - 1, oj = jv < ny ? jv : ny - 1;
+      z += p.datum[(oj / TY) * p.tiles_x + oi / TX] - dT;
+    }
+    sm.zv[r] = z;
   }
   auto zb = [&](int iv, int jv) -> R { return sm.zv[(jv - j0 + 2) * VX + (iv - i0 + 2)]; };
   const R dtr = R(dt);
@@ -588,15 +623,24 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
       const R sw = zb(i, j), se = zb(i + 1, j), nw = zb(i, j + 1), ne = zb(i + 1, j + 1);
       const R z1x = (R(0.5) * (ne + se) - R(0.5) * (nw + sw)) * K<R>::inv_2s3;
       const R z1y = (R(0.5) * (nw + ne) - R(0.5) * (sw + se)) * K<R>::inv_2s3;
-      const R e0 = h0 + sm.z0[pos];
+      const R z0c = sm.z0[pos];
+      const R e0 = h0 + z0c;
 #pragma unroll
       for (int d = 1; d <= 2; ++d) {
         const int off = d == 1 ? 1 : RX;
         const R zs = d == 1 ? z1x : z1y;
-        const R em = sm.c[0][pos - off] + sm.z0[pos - off];
-        const R ep = sm.c[0][pos + off] + sm.z0[pos + off];
+        // forward and backward differences of the mean free surface; FP32 sums the
+        // depth and bed differences (the latter exact), free of the datum
+        R dp, dm;
+        if constexpr (sizeof(R) == 8) {
+          dp = (sm.c[0][pos + off] + sm.z0[pos + off]) - e0;
+          dm = e0 - (sm.c[0][pos - off] + sm.z0[pos - off]);
+        } else {
+          dp = (sm.c[0][pos + off] - h0) + (sm.z0[pos + off] - z0c);
+          dm = (h0 - sm.c[0][pos - off]) + (z0c - sm.z0[pos - off]);
+        }
         const R e1 = v[d] + zs;
-        const R le = minmod3(e1, (ep - e0) * K<R>::inv_s3, (e0 - em) * K<R>::inv_s3);
+        const R le = minmod3(e1, dp * K<R>::inv_s3, dm * K<R>::inv_s3);
         v[d] = le != e1 ? le - zs : v[d];
         if (!(dirs & d)) continue;  // discharge slopes only where they are used
 #pragma unroll
@@ -638,7 +682,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
   // ring item: W ring publishes its east side, S ring its north side; E and N ring
   // cells keep their west / south side for the tile's east / north faces
   Side<R> sb_;
-  sb_.h = sb_.u = sb_.v = sb_.z = R(0);
+  sb_.h = sb_.u = sb_.v = sb_.z = sb_.m = R(0);
   if (b_in) {
     const int oa = rb_side == 0 ? 1 : (rb_side == 1 ? -1 : 0);
     const int ob = rb_side == 2 ? 1 : (rb_side == 3 ? -1 : 0);
@@ -700,7 +744,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
       const R qxE = se_.h * se_.u, qxW = sw_.h * sw_.u, qyE = se_.h * se_.v, qyW = sw_.h * sw_.v;
       const R qb0 = R(0.5) * (qxE + qxW), qb1 = (qxE - qxW) * K<R>::inv_2s3;
       const R rb0 = R(0.5) * (qyE + qyW), rb1 = (qyE - qyW) * K<R>::inv_2s3;
-      const R zb1 = (se_.z - sw_.z) * K<R>::inv_2s3;
+      const R zb1 = ((se_.z - sw_.z) + (se_.m - sw_.m)) * K<R>::inv_2s3;
       R Fp[3], Fm[3];
       gauss_flux(g, ht, hb0 + hb1, qb0 + qb1, rb0 + rb1, Fp);
       gauss_flux(g, ht, hb0 - hb1, qb0 - qb1, rb0 - rb1, Fm);
@@ -714,7 +758,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
       const R qxN = sn_.h * sn_.u, qxS = ss_.h * ss_.u, qyN = sn_.h * sn_.v, qyS = ss_.h * ss_.v;
       const R qb0 = R(0.5) * (qxN + qxS), qb1 = (qxN - qxS) * K<R>::inv_2s3;
       const R rb0 = R(0.5) * (qyN + qyS), rb1 = (qyN - qyS) * K<R>::inv_2s3;
-      const R zb1 = (sn_.z - ss_.z) * K<R>::inv_2s3;
+      const R zb1 = ((sn_.z - ss_.z) + (sn_.m - ss_.m)) * K<R>::inv_2s3;
       R Gp[3], Gm[3];
       gauss_flux(g, ht, hb0 + hb1, rb0 + rb1, qb0 + qb1, Gp);
       gauss_flux(g, ht, hb0 - hb1, rb0 - rb1, qb0 - qb1, Gm);
@@ -1008,8 +1052,8 @@ __global__ void init_kernel(Params<R> p, const double* __restrict__ src, int mod
     }
   } else {
     R z0, z1x, z1y;
-    bed(p, i, j, z0, z1x, z1y);
-    const R h0 = R(eta) - z0;
+    bed(p, i, j, z0, z1x, z1y);  // in the frame of the tile's datum
+    const R h0 = R((eta - double(tile_datum(p, i, j))) - double(z0));
     if (h0 > R(0)) {
       c[0] = h0;
       c[1] = -z1x;
@@ -1083,8 +1127,9 @@ __global__ void field_kernel(Params<R> p, const R* __restrict__ u, int field, R*
   const R h0 = u[k];
   if (field == 9) {
     R z0, z1x, z1y;
-    bed(p, int(k % p.nx), int(k / p.nx), z0, z1x, z1y);
-    out[k] = h0 + z0;
+    const int i = int(k % p.nx), j = int(k / p.nx);
+    bed(p, i, j, z0, z1x, z1y);
+    out[k] = R(double(h0) + double(z0) + double(tile_datum(p, i, j)));
   } else {
     const R q = u[(field == 10 ? 3 : 6) * p.n + k];
     out[k] = h0 > p.h_tol ? q / h0 : R(0);

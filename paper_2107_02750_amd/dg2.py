@@ -21,7 +21,8 @@ MAX_SEGMENTS, MAX_KNOTS = 64, 8192
 SYMBOLS = ("dg2_workspace_size", "dg2_init", "dg2_step", "dg2_run", "dg2_read",
            "dg2_get_scalars", "dg2_next_dt", "dg2_state_bytes", "dg2_get_state",
            "dg2_set_state", "dg2_set_timing", "dg2_get_timing", "dg2_kernel_info",
-           "dg2_last_error", "dg2_init_error", "dg2_destroy")
+           "dg2_bed_info", "dg2_plan_bed_datum", "dg2_tile_grid", "dg2_last_error",
+           "dg2_init_error", "dg2_destroy")
 
 _dp = C.POINTER(C.c_double)
 
@@ -30,7 +31,7 @@ class Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("g", C.c_double),
                 ("cfl", C.c_double), ("h_tol", C.c_double), ("dt_dry", C.c_double),
                 ("t0", C.c_double), ("precision", C.c_int32), ("limiter", C.c_int32),
-                ("edge_kind", C.c_int32 * 4)]
+                ("edge_kind", C.c_int32 * 4), ("bed_datum", C.c_int32)]
 
 
 class Boundary(C.Structure):
@@ -72,6 +73,9 @@ def load(path: str = LIB_PATH):
     lib.dg2_set_timing.argtypes = [vp, i32]
     lib.dg2_get_timing.argtypes = [vp, C.POINTER(i64), _dp, _dp]
     lib.dg2_kernel_info.argtypes = [vp] + [C.POINTER(i32)] * 5
+    lib.dg2_bed_info.argtypes = [vp, _dp, _dp]
+    lib.dg2_plan_bed_datum.argtypes = [C.POINTER(Config), _dp, _dp, _dp, _dp, _dp]
+    lib.dg2_tile_grid.argtypes = [C.POINTER(Config)] + [C.POINTER(i32)] * 4
     lib.dg2_last_error.argtypes = [vp]
     lib.dg2_last_error.restype = C.c_char_p
     lib.dg2_init_error.argtypes = []
@@ -90,15 +94,19 @@ def _ptr(a):
     return a.ctypes.data_as(_dp) if a is not None else None
 
 
-def make_config(sc, precision: int) -> Config:
+def make_config(sc, precision: int, bed_datum: bool | None = None) -> Config:
+    """The C configuration of a scenario. bed_datum (FP32 only) defaults to on."""
+    if bed_datum is None:
+        bed_datum = precision == FP32
     return Config(int(sc.nx), int(sc.ny), float(sc.dx), float(sc.g), float(sc.cfl),
                   float(sc.h_tol), float(sc.dt_dry), float(sc.t0), int(precision),
-                  int(sc.limiter), (C.c_int32 * 4)(*[int(k) for k in sc.edge_kind]))
+                  int(sc.limiter), (C.c_int32 * 4)(*[int(k) for k in sc.edge_kind]),
+                  int(bool(bed_datum)))
 
 
-def workspace_bytes(sc, precision: int = FP64) -> int:
+def workspace_bytes(sc, precision: int = FP64, bed_datum: bool | None = None) -> int:
     lib = load()
-    cfg = make_config(sc, precision)
+    cfg = make_config(sc, precision, bed_datum)
     out = C.c_size_t()
     rc = lib.dg2_workspace_size(C.byref(cfg), C.byref(out))
     if rc != 0:
@@ -106,14 +114,45 @@ def workspace_bytes(sc, precision: int = FP64) -> int:
     return out.value
 
 
+def tile_grid(sc, precision: int) -> dict:
+    """Tile shape and tile counts of the stage kernels (host only)."""
+    lib = load()
+    cfg = make_config(sc, precision)
+    v = [C.c_int32() for _ in range(4)]
+    rc = lib.dg2_tile_grid(C.byref(cfg), *[C.byref(x) for x in v])
+    if rc != 0:
+        raise DG2Error(rc, "bad configuration")
+    return dict(zip(("tile_x", "tile_y", "tiles_x", "tiles_y"), [x.value for x in v]))
+
+
+def plan_bed_datum(sc) -> dict:
+    """The FP32 datum plan of a scenario's bed, as dg2_init builds it (host only):
+    stored relative bed, per-tile datums (tiles_y x tiles_x), quantum, largest local
+    elevation."""
+    lib = load()
+    cfg = make_config(sc, FP32, True)
+    tg = tile_grid(sc, FP32)
+    zv = _f64(sc.zv)
+    zrel = np.empty_like(zv)
+    datum = np.empty((tg["tiles_y"], tg["tiles_x"]))
+    q, b = C.c_double(), C.c_double()
+    rc = lib.dg2_plan_bed_datum(C.byref(cfg), _ptr(zv), _ptr(zrel), _ptr(datum), C.byref(q),
+                                C.byref(b))
+    if rc != 0:
+        raise DG2Error(rc, "bed datum plan")
+    return dict(zrel=zrel, datum=datum, quantum=q.value, max_local=b.value, **tg)
+
+
 class DG2:
     """One simulation on the GPU, built from a scenario (see the seeded generators):
     attributes nx, ny, dx, g, cfl, h_tol, dt_dry, t0, limiter, edge_kind, zv, manning,
-    manning_scalar, init_mode, init_data, eta_level, boundaries."""
+    manning_scalar, init_mode, init_data, eta_level, boundaries. FP32 stores the bed
+    relative to per-tile datums unless bed_datum is False."""
 
     PLANES = ("h0", "h1x", "h1y", "qx0", "qx1x", "qx1y", "qy0", "qy1x", "qy1y")
 
-    def __init__(self, sc, precision: int = FP64, device: str = "cuda:0", stream=None):
+    def __init__(self, sc, precision: int = FP64, device: str = "cuda:0", stream=None,
+                 bed_datum: bool | None = None):
         import torch
         lib = load()
         self._lib = lib
@@ -122,7 +161,7 @@ class DG2:
         self.dtype = np.float32 if precision == FP32 else np.float64
         self.torch_dtype = torch.float32 if precision == FP32 else torch.float64
         self.device = torch.device(device)
-        cfg = make_config(sc, precision)
+        cfg = make_config(sc, precision, bed_datum)
         ws = C.c_size_t()
         rc = lib.dg2_workspace_size(C.byref(cfg), C.byref(ws))
         if rc != 0:
@@ -221,6 +260,11 @@ class DG2:
         a, b = C.c_double(), C.c_double()
         self._check(self._lib.dg2_get_timing(self._h, C.byref(s), C.byref(a), C.byref(b)))
         return dict(steps=s.value, ms_stage1=a.value, ms_stage2=b.value)
+
+    def bed_info(self) -> dict:
+        q, b = C.c_double(), C.c_double()
+        self._check(self._lib.dg2_bed_info(self._h, C.byref(q), C.byref(b)))
+        return dict(quantum=q.value, max_local=b.value)
 
     def kernel_info(self) -> dict:
         v = [C.c_int32() for _ in range(5)]
