@@ -100,39 +100,53 @@ def cpu_baseline(sc, budget_s):
 
 
 def precision_form(dg2, S, n, t_end):
-    """The urban terrain (flat ground with building blocks, dry start, 1 m deep inflow at
-    2 m/s along the west edge) run to t_end in FP64 and in FP32, with the bed stored
-    relative to per-tile datums and stored absolute, at its own elevation and raised by
-    1000 m: the FP32 depth error against the FP64 run, the mass-balance drift of each
-    run, and the cell-update rate."""
+    """FP32 with per-tile bed datums against FP64.
+
+    Urban terrain (flat ground with building blocks, dry start, 1 m deep inflow at 2 m/s
+    along the west edge), both precisions advanced side by side to checkpoints up to
+    t_end: FP32 depth error against the FP64 run at each checkpoint, mass-balance
+    drift at the end, cell-update rates. Then the all-wet channel terrain raised by
+    1000 m, 60 s: FP32 with datums against FP32 storing absolute elevations."""
     import torch
     sc = S.urban_blocks(n=n)
     res = {"workload": f"urban blocks {n}x{n}, dx=2 m, 4000 blocks, 1 m at 2 m/s inflow on W, "
-                       "n=0.02, dry start", "cells": n * n, "t_end": t_end}
-
-    def one(s, prec, datum):
-        sim = dg2.DG2(s, prec, bed_datum=datum)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        steps = sim.run(t_end)
-        el = time.perf_counter() - t0
+                       "n=0.02, dry start", "cells": n * n}
+    sims = {"fp64": dg2.DG2(sc, dg2.FP64), "fp32_datum": dg2.DG2(sc, dg2.FP32)}
+    secs = {k: 0.0 for k in sims}
+    steps = {k: 0 for k in sims}
+    errs = []
+    for tc in (10.0, 60.0, t_end):
+        for k, sim in sims.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            steps[k] += sim.run(tc)
+            secs[k] += time.perf_counter() - t0
+        d = sims["fp32_datum"].read(0).astype(np.float64) - sims["fp64"].read(0)
+        errs.append({"t": tc, "max_depth_error_m": float(np.abs(d).max()),
+                     "rms_depth_error_m": float(np.sqrt(np.mean(d * d)))})
+    for k, sim in sims.items():
         sc_ = sim.scalars()
-        bal = sc_["mass"] - sc_["mass_in"] + sc_["mass_out"] - sc_["mass_clip"]  # M0 = 0
-        r = {"value": n * n * steps / el, "unit": "cell-updates/s", "steps": steps,
-             "mass_balance_rel": bal / max(sc_["mass"], sc_["mass_in"]),
-             "bed_quantum_m": sim.bed_info()["quantum"]}
-        return sim.read(0).astype(np.float64), r
+        bal = sc_["mass"] - sc_["mass_in"] + sc_["mass_out"] - sc_["mass_clip"]  # dry start
+        res[k] = {"value": n * n * steps[k] / secs[k], "unit": "cell-updates/s",
+                  "steps": steps[k], "mass_balance_rel": bal / max(sc_["mass"], sc_["mass_in"]),
+                  "bed_quantum_m": sim.bed_info()["quantum"]}
+    res["fp32_datum"]["depth_error_vs_fp64"] = errs
+    del sims
 
-    h64, res["fp64"] = one(sc, dg2.FP64, False)
-    hi = sc.replace(zv=sc.zv + 1000.0)
-    for key, s, datum in (("fp32_datum", sc, True), ("fp32_absolute", sc, False),
-                          ("fp32_datum_bed_plus_1000m", hi, True),
-                          ("fp32_absolute_bed_plus_1000m", hi, False)):
-        h, r = one(s, dg2.FP32, datum)
-        d = h - h64
-        r["max_depth_error_m"] = float(np.abs(d).max())
-        r["rms_depth_error_m"] = float(np.sqrt(np.mean(d * d)))
-        res[key] = r
+    hi = S.fbm_channel_wet(n=1024)
+    hi = hi.replace(zv=hi.zv + 1000.0)  # initial depths are given, not levels
+    ref = dg2.DG2(hi, dg2.FP64)
+    ref.run(60.0)
+    h64 = ref.read(0)
+    elev = {"workload": "the all-wet channel terrain with the bed raised by 1000 m, t=60 s"}
+    for key, datum in (("fp32_datum", True), ("fp32_absolute", False)):
+        sim = dg2.DG2(hi, dg2.FP32, bed_datum=datum)
+        sim.run(60.0)
+        d = sim.read(0).astype(np.float64) - h64
+        elev[key] = {"max_depth_error_m": float(np.abs(d).max()),
+                     "rms_depth_error_m": float(np.sqrt(np.mean(d * d))),
+                     "bed_quantum_m": sim.bed_info()["quantum"]}
+    res["bed_plus_1000m"] = elev
     res["error_vs"] = "the FP64 GPU run on the same bed (which matches the FP64 oracle to 1e-12)"
     return res
 
@@ -243,10 +257,13 @@ def main():
               f"wet {wet:.4f}", file=sys.stderr, flush=True)
         out["precision_form"] = precision_form(dg2, S, args.n_urban, args.t_urban)
         pf = out["precision_form"]
-        print(f"[bench] urban {pf['cells']} cells to t={pf['t_end']:.0f} s: FP32 datum max depth err "
-              f"{pf['fp32_datum']['max_depth_error_m']:.3g} m (bed +1000 m: "
-              f"{pf['fp32_datum_bed_plus_1000m']['max_depth_error_m']:.3g} m; absolute FP32 there: "
-              f"{pf['fp32_absolute_bed_plus_1000m']['max_depth_error_m']:.3g} m)", file=sys.stderr, flush=True)
+        e = pf["fp32_datum"]["depth_error_vs_fp64"]
+        print(f"[bench] urban {pf['cells']} cells: FP32 datum max/rms depth err "
+              + ", ".join(f"t={x['t']:.0f} s {x['max_depth_error_m']:.2g}/{x['rms_depth_error_m']:.2g} m"
+                          for x in e)
+              + f"; bed +1000 m, t=60 s: datum {pf['bed_plus_1000m']['fp32_datum']['max_depth_error_m']:.2g} m, "
+              f"absolute {pf['bed_plus_1000m']['fp32_absolute']['max_depth_error_m']:.2g} m",
+              file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
         print(f"[bench] CPU oracle {out['cpu_baseline']['value']:.4g} cell-updates/s on "
               f"{out['cpu_baseline']['cores']} threads", file=sys.stderr, flush=True)
