@@ -11,7 +11,8 @@ Also reported, on the same line: the FP32 instantiation on the same workload wit
 depth error against the FP64 path, the same terrain as configured (dry start, channel
 inflow hydrograph) timed from a snapshot at t = 3600 s, the urban precision run (FP32
 with per-tile bed datums against FP64: depth error, mass drift, also with the bed raised
-by 1000 m), the stage-kernel durations from HIP events recorded on the launch stream
+by 1000 m), the batched run of 64 uneven scenarios against running them one at a
+time, the stage-kernel durations from HIP events recorded on the launch stream
 with the roofline of the dominant kernel, and the FP64 CPU oracle timed on this host's
 cores on a bounded sample.
 """
@@ -151,6 +152,49 @@ def precision_form(dg2, S, n, t_end):
     return res
 
 
+def batched(dg2, S, count, t_end):
+    """count scenarios of uneven size (seeded; FP32 with bed datums, FP64 mass ledgers)
+    run to t_end as one batch (shared launches from a HIP graph), then the same
+    scenarios one after another; aggregate cell-updates/s of both, and whether every
+    member ends bitwise where it does alone."""
+    import torch
+    scs = S.batch_scenarios(count=count, t_end=t_end)
+    cells = [sc.nx * sc.ny for sc in scs]
+    stream = torch.cuda.Stream()
+    sims = [dg2.DG2(sc, dg2.FP32, stream=stream) for sc in scs]
+    batch = dg2.Batch(sims, graph_steps=32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, pairs = batch.run(t_end)
+    el = time.perf_counter() - t0
+    batch.close()
+    work = sum(c * k for c, k in zip(cells, steps))
+    drift = 0.0
+    for sim in sims:
+        s_ = sim.scalars()
+        bal = s_["mass"] - s_["mass_in"] + s_["mass_out"] - s_["mass_clip"]  # dry start
+        drift = max(drift, abs(bal) / max(s_["mass"], s_["mass_in"], 1e-300))
+    seq_el = 0.0
+    equal = True
+    for sc, sim in zip(scs, sims):
+        one = dg2.DG2(sc, dg2.FP32, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one.run(t_end)
+        seq_el += time.perf_counter() - t0
+        equal = equal and one.get_state() == sim.get_state()
+        del one
+    return {"workload": f"{count} fBm channel scenarios, sides U{{256..1024}} (total "
+                        f"{sum(cells)} cells), dx U[2,10] m, n U(0.015,0.06), inflow peaks "
+                        f"U(5,100) m^3/s, dry start, each run to t={t_end:.0f} s, FP32 with bed datums",
+            "value": work / el, "unit": "cell-updates/s", "seconds": el,
+            "member_steps": {"min": min(steps), "max": max(steps), "total": sum(steps)},
+            "launch_pairs": pairs,
+            "one_at_a_time": {"value": work / seq_el, "seconds": seq_el},
+            "speedup": seq_el / el, "bitwise_equal_to_one_at_a_time": equal,
+            "max_mass_balance_rel": drift}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +204,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--n-urban", type=int, default=2048, help="grid side of the urban precision run")
     ap.add_argument("--t-urban", type=float, default=600.0, help="simulated seconds of the urban run")
+    ap.add_argument("--batch-count", type=int, default=64, help="scenarios in the batched run")
+    ap.add_argument("--batch-t-end", type=float, default=1800.0, help="simulated seconds per scenario")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the FP64 timed region (for profiler runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -264,6 +310,12 @@ def main():
               + f"; bed +1000 m, t=60 s: datum {pf['bed_plus_1000m']['fp32_datum']['max_depth_error_m']:.2g} m, "
               f"absolute {pf['bed_plus_1000m']['fp32_absolute']['max_depth_error_m']:.2g} m",
               file=sys.stderr, flush=True)
+        out["batched"] = batched(dg2, S, args.batch_count, args.batch_t_end)
+        bt = out["batched"]
+        print(f"[bench] batched {args.batch_count} scenarios: {bt['value']:.4g} cell-updates/s "
+              f"({bt['seconds']:.1f} s), one at a time {bt['one_at_a_time']['value']:.4g} "
+              f"({bt['one_at_a_time']['seconds']:.1f} s), bitwise equal: "
+              f"{bt['bitwise_equal_to_one_at_a_time']}", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
         print(f"[bench] CPU oracle {out['cpu_baseline']['value']:.4g} cell-updates/s on "
               f"{out['cpu_baseline']['cores']} threads", file=sys.stderr, flush=True)

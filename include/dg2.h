@@ -205,6 +205,33 @@ int dg2_plan_bed_datum(const dg2_config *cfg, const double *zv, double *zrel, do
 int dg2_tile_grid(const dg2_config *cfg, int32_t *tile_x, int32_t *tile_y, int32_t *tiles_x,
                   int32_t *tiles_y);
 
+/* ---- Batched scenarios --------------------------------------------------------
+ * A batch advances many independent contexts (flood scenarios of any grid size) with
+ * shared launches: each step launches the two stage kernels once over the tiles of
+ * every member, and every member keeps its own time, CFL time step, state, mass
+ * ledger and health word. For each member a batch step is bitwise the same as a
+ * dg2_step of that member alone (no dt_max). Steps are issued by replaying a HIP graph
+ * of graph_steps steps (an even number, 2..256) captured on the members' stream.
+ *  - members: n (1..DG2_MAX_BATCH) distinct contexts of one precision, all created on
+ *    the same stream. The batch borrows them: they must outlive it, and while it
+ *    exists they may be read and queried but not stepped, run or restored alone.
+ *  - The batch allocates its launch table and status buffers (a few hundred KB of
+ *    device memory and a little pinned host memory); dg2_batch_destroy frees them.
+ *  - Errors: DG2_E_ARG (bad list, mixed precision or streams, a repeated member),
+ *    DG2_E_DEVICE, DG2_E_NUMERIC (a member's health word tripped; the message names
+ *    it). */
+#define DG2_MAX_BATCH 256
+typedef struct dg2_batch dg2_batch;
+int dg2_batch_create(dg2_ctx *const *members, int32_t n, int32_t graph_steps, dg2_batch **out);
+/* 'steps' steps of every member, issued without waiting for the device */
+int dg2_batch_step(dg2_batch *b, int32_t steps);
+/* Run every member to t_end (each lands exactly on it, as dg2_run does); members that
+ * reach it leave the launches. member_steps (n int64, may be NULL) receives the steps
+ * each member took; launches (may be NULL) the stage-kernel launch pairs issued. */
+int dg2_batch_run(dg2_batch *b, double t_end, int64_t *member_steps, int64_t *launches);
+const char *dg2_batch_last_error(const dg2_batch *b);
+void dg2_batch_destroy(dg2_batch *b);
+
 const char *dg2_last_error(const dg2_ctx *c);
 const char *dg2_init_error(void);
 

@@ -87,6 +87,27 @@ struct dg2_ctx {
   size_t ev_used;
   int64_t t_steps;
   double t_ms1, t_ms2;
+  bool in_batch;       // borrowed by a batch: not stepped alone
+  std::string err;
+};
+
+struct dg2_batch {
+  std::vector<dg2_ctx*> members;
+  std::vector<int> active;   // member indices in the current launch table
+  hipStream_t stream;
+  bool fp32;
+  int graph_steps;
+  void* d_table;             // dg2k::BatchTable<R>
+  size_t table_bytes;
+  double* d_t;               // status: time and health of each table entry
+  int* d_health;
+  double* h_t;               // pinned mirrors
+  int* h_health;
+  int grid;                  // blocks per launch of the current table
+  double t_end;              // t_end of the current table
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  bool graph_ok;
   std::string err;
 };
 
@@ -317,9 +338,266 @@ int init_device(dg2_ctx* c, const double* zv, const double* man, int mode, const
   return rc;
 }
 
+int bfail(dg2_batch* b, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  b->err = buf;
+  return code;
+}
+
+#define BHIPC(b, call)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return bfail(b, DG2_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// launch table of the active members: phase 0 uses each member's current parity
+template <typename R>
+int batch_table(dg2_batch* b) {
+  std::vector<char> buf(sizeof(dg2k::BatchTable<R>), 0);
+  auto* tab = reinterpret_cast<dg2k::BatchTable<R>*>(buf.data());
+  tab->n = (int)b->active.size();
+  int total = 0;
+  for (int k = 0; k < tab->n; ++k) {
+    dg2_ctx* c = b->members[b->active[k]];
+    tab->start[k] = total;
+    total += c->L.n_tiles;
+    for (int ph = 0; ph < 2; ++ph) {
+      const int keep = c->parity;
+      c->parity = keep ^ ph;
+      Params<R> p = params<R>(c);
+      c->parity = keep;
+      p.dt_max = 0.0;
+      p.t_end = b->t_end;
+      tab->p[ph][k] = p;
+    }
+  }
+  tab->start[tab->n] = total;
+  tab->total = total;
+  tab->per_xcd = (total + dg2k::NXCD - 1) / dg2k::NXCD;
+  b->grid = tab->per_xcd * dg2k::NXCD;
+  BHIPC(b, hipMemcpyAsync(b->d_table, buf.data(), buf.size(), hipMemcpyHostToDevice, b->stream));
+  BHIPC(b, hipStreamSynchronize(b->stream));
+  return DG2_OK;
+}
+
+template <typename R>
+int batch_launch_step(dg2_batch* b, int phase) {
+  const auto* tab = reinterpret_cast<const dg2k::BatchTable<R>*>(b->d_table);
+  const dim3 grid(b->grid), block(dg2k::Geo<R>::NT);
+  hipLaunchKernelGGL((dg2k::stage_kernel_batch<R, 1>), grid, block, 0, b->stream, tab, phase);
+  BHIPC(b, hipGetLastError());
+  hipLaunchKernelGGL((dg2k::stage_kernel_batch<R, 2>), grid, block, 0, b->stream, tab, phase);
+  BHIPC(b, hipGetLastError());
+  return DG2_OK;
+}
+
+void batch_drop_graph(dg2_batch* b) {
+  if (b->graph_ok) {
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
+    b->graph_ok = false;
+  }
+}
+
+// (re)build the table for the active members and capture graph_steps steps of it
+int batch_prepare(dg2_batch* b, double t_end) {
+  batch_drop_graph(b);
+  b->t_end = t_end;
+  int rc = b->fp32 ? batch_table<float>(b) : batch_table<double>(b);
+  if (rc) return rc;
+  if (b->active.empty()) return DG2_OK;
+  BHIPC(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  for (int s = 0; s < b->graph_steps && rc == DG2_OK; ++s)
+    rc = b->fp32 ? batch_launch_step<float>(b, s & 1) : batch_launch_step<double>(b, s & 1);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return bfail(b, DG2_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return bfail(b, DG2_E_DEVICE, "graph instantiation: %s", hipGetErrorString(e));
+  }
+  b->graph = g;
+  b->graph_ok = true;
+  return DG2_OK;
+}
+
+// issue 'steps' steps of the active members (graph replays, then single steps)
+int batch_issue(dg2_batch* b, long long steps) {
+  if (b->active.empty() || steps <= 0) return DG2_OK;
+  const long long reps = steps / b->graph_steps, rest = steps % b->graph_steps;
+  for (long long r = 0; r < reps; ++r) BHIPC(b, hipGraphLaunch(b->exec, b->stream));
+  int rc = DG2_OK;
+  for (long long s = 0; s < rest && rc == DG2_OK; ++s)
+    rc = b->fp32 ? batch_launch_step<float>(b, (int)(s & 1)) : batch_launch_step<double>(b, (int)(s & 1));
+  if (rc) return rc;
+  if (steps & 1)
+    for (int k : b->active) b->members[k]->parity ^= 1;
+  if (rest & 1) return batch_prepare(b, b->t_end);  // phase 0 must match the parities again
+  return DG2_OK;
+}
+
+// time and health of the active members (waits)
+int batch_status(dg2_batch* b) {
+  const int n = (int)b->active.size();
+  if (n == 0) return DG2_OK;
+  const unsigned blocks = (unsigned)((n + 63) / 64);
+  if (b->fp32)
+    hipLaunchKernelGGL((dg2k::batch_status_kernel<float>), dim3(blocks), dim3(64), 0, b->stream,
+                       reinterpret_cast<const dg2k::BatchTable<float>*>(b->d_table), 0, b->d_t, b->d_health);
+  else
+    hipLaunchKernelGGL((dg2k::batch_status_kernel<double>), dim3(blocks), dim3(64), 0, b->stream,
+                       reinterpret_cast<const dg2k::BatchTable<double>*>(b->d_table), 0, b->d_t, b->d_health);
+  BHIPC(b, hipGetLastError());
+  BHIPC(b, hipMemcpyAsync(b->h_t, b->d_t, n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  BHIPC(b, hipMemcpyAsync(b->h_health, b->d_health, n * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  BHIPC(b, hipStreamSynchronize(b->stream));
+  for (int k = 0; k < n; ++k) {
+    const int h = b->h_health[k];
+    if (h & 1) return bfail(b, DG2_E_NUMERIC, "member %d: NaN in the state", b->active[k]);
+    if (h & 2) return bfail(b, DG2_E_NUMERIC, "member %d: CFL time step below 1e-12 s", b->active[k]);
+  }
+  return DG2_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int dg2_batch_create(dg2_ctx* const* members, int32_t n, int32_t graph_steps, dg2_batch** out) {
+  g_init_err.clear();
+  if (!out) return DG2_E_ARG;
+  *out = nullptr;
+  if (!members || n < 1 || n > DG2_MAX_BATCH || n > dg2k::MAX_BATCH) {
+    g_init_err = "bad member list";
+    return DG2_E_ARG;
+  }
+  if (graph_steps < 2 || graph_steps > 256 || (graph_steps & 1)) {
+    g_init_err = "graph_steps must be even, 2..256";
+    return DG2_E_ARG;
+  }
+  for (int k = 0; k < n; ++k) {
+    const dg2_ctx* c = members[k];
+    if (!c || c->in_batch || c->fp32 != members[0]->fp32 || c->stream != members[0]->stream) {
+      g_init_err = "members must be distinct free contexts of one precision on one stream";
+      return DG2_E_ARG;
+    }
+    for (int j = 0; j < k; ++j)
+      if (members[j] == c) {
+        g_init_err = "repeated member";
+        return DG2_E_ARG;
+      }
+  }
+  if (!members[0]->stream) {
+    g_init_err = "a batch is captured into a HIP graph: its stream must not be the null stream";
+    return DG2_E_ARG;
+  }
+  dg2_batch* b = new (std::nothrow) dg2_batch();
+  if (!b) return DG2_E_ARG;
+  b->members.assign(members, members + n);
+  b->stream = members[0]->stream;
+  b->fp32 = members[0]->fp32;
+  b->graph_steps = graph_steps;
+  b->table_bytes = b->fp32 ? sizeof(dg2k::BatchTable<float>) : sizeof(dg2k::BatchTable<double>);
+  b->t_end = INFINITY;
+  b->graph_ok = false;
+  hipError_t e = hipMalloc(&b->d_table, b->table_bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_t, n * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_health, n * sizeof(int));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_t, n * sizeof(double));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_health, n * sizeof(int));
+  if (e != hipSuccess) {
+    g_init_err = std::string("batch buffers: ") + hipGetErrorString(e);
+    dg2_batch_destroy(b);
+    return DG2_E_DEVICE;
+  }
+  for (int k = 0; k < n; ++k) {
+    b->active.push_back(k);
+    members[k]->in_batch = true;
+  }
+  int rc = batch_prepare(b, INFINITY);
+  if (rc) {
+    g_init_err = b->err;
+    dg2_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return DG2_OK;
+}
+
+int dg2_batch_step(dg2_batch* b, int32_t steps) {
+  if (!b || steps < 0) return DG2_E_ARG;
+  if (b->active.size() != b->members.size() || !std::isinf(b->t_end)) {
+    b->active.clear();
+    for (int k = 0; k < (int)b->members.size(); ++k) b->active.push_back(k);
+    int rc = batch_prepare(b, INFINITY);
+    if (rc) return rc;
+  }
+  return batch_issue(b, steps);
+}
+
+int dg2_batch_run(dg2_batch* b, double t_end, int64_t* member_steps, int64_t* launches) {
+  if (!b || std::isnan(t_end)) return DG2_E_ARG;
+  const int n = (int)b->members.size();
+  std::vector<long long> s0(n);
+  for (int k = 0; k < n; ++k) {
+    dg2_ctx* c = b->members[k];
+    int rc = pull_ctrl(c);
+    if (rc) return bfail(b, rc, "member %d: %s", k, c->err.c_str());
+    if (!(t_end >= c->h_ctrl->t[c->parity]))
+      return bfail(b, DG2_E_ARG, "member %d: t_end %g is before t %g", k, t_end, c->h_ctrl->t[c->parity]);
+    s0[k] = c->h_ctrl->step[c->parity];
+  }
+  b->active.clear();
+  for (int k = 0; k < n; ++k)
+    if (b->members[k]->h_ctrl->t[b->members[k]->parity] < t_end) b->active.push_back(k);
+  int rc = batch_prepare(b, t_end);
+  long long pairs = 0;
+  while (rc == DG2_OK && !b->active.empty()) {
+    if ((rc = batch_issue(b, b->graph_steps))) break;
+    pairs += b->graph_steps;
+    if ((rc = batch_status(b))) break;
+    std::vector<int> keep;
+    for (int k = 0; k < (int)b->active.size(); ++k)
+      if (b->h_t[k] < t_end) keep.push_back(b->active[k]);
+    if (keep.size() != b->active.size()) {
+      b->active = keep;
+      rc = batch_prepare(b, t_end);
+    }
+  }
+  if (launches) *launches = pairs;
+  if (member_steps) {
+    for (int k = 0; k < n; ++k) {
+      dg2_ctx* c = b->members[k];
+      if (pull_ctrl(c) == DG2_OK) member_steps[k] = c->h_ctrl->step[c->parity] - s0[k];
+    }
+  }
+  return rc;
+}
+
+const char* dg2_batch_last_error(const dg2_batch* b) { return b ? b->err.c_str() : g_init_err.c_str(); }
+
+void dg2_batch_destroy(dg2_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  batch_drop_graph(b);
+  for (dg2_ctx* c : b->members) c->in_batch = false;
+  if (b->d_table) (void)hipFree(b->d_table);
+  if (b->d_t) (void)hipFree(b->d_t);
+  if (b->d_health) (void)hipFree(b->d_health);
+  if (b->h_t) (void)hipHostFree(b->h_t);
+  if (b->h_health) (void)hipHostFree(b->h_health);
+  delete b;
+}
+
 
 int dg2_workspace_size(const dg2_config* cfg, size_t* bytes) {
   if (!bytes) return DG2_E_ARG;
@@ -440,6 +718,7 @@ int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, dou
   x->ev_used = 0;
   x->t_steps = 0;
   x->t_ms1 = x->t_ms2 = 0;
+  x->in_batch = false;
   auto dev = [&](hipError_t e, const char* what) {
     if (e == hipSuccess) return false;
     g_init_err = std::string(what) + ": " + hipGetErrorString(e);
@@ -477,6 +756,7 @@ int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, dou
 
 int dg2_step(dg2_ctx* c, double dt_max, double* dt_used) {
   if (!c) return DG2_E_ARG;
+  if (c->in_batch) return fail(c, DG2_E_STATE, "context belongs to a batch");
   const int p = c->parity;
   int rc = step_any(c, dt_max, INFINITY);
   if (rc) return rc;
@@ -490,6 +770,7 @@ int dg2_step(dg2_ctx* c, double dt_max, double* dt_used) {
 
 int dg2_run(dg2_ctx* c, double t_end, int64_t* steps_taken) {
   if (!c) return DG2_E_ARG;
+  if (c->in_batch) return fail(c, DG2_E_STATE, "context belongs to a batch");
   int rc = pull_ctrl(c);
   if (rc) return rc;
   const double t_start = c->h_ctrl->t[c->parity];
@@ -612,6 +893,7 @@ int dg2_get_state(dg2_ctx* c, void* host_dst) {
 
 int dg2_set_state(dg2_ctx* c, const void* host_src) {
   if (!c || !host_src) return DG2_E_ARG;
+  if (c->in_batch) return fail(c, DG2_E_STATE, "context belongs to a batch");
   const char* b = reinterpret_cast<const char*>(host_src);
   int64_t hdr[8];
   std::memcpy(hdr, b, sizeof hdr);

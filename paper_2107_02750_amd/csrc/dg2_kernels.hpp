@@ -966,12 +966,12 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
   }
 }
 
+// One stage over tile `tile` of the context described by p: the step's time step, the
+// control-block update (stage 1, tile 0), then the tile's work (or, once the run has
+// reached t_end, a copy of the state that keeps the buffer parity).
 template <typename R, int STAGE>
-__global__ __launch_bounds__(Geo<R>::NT, Tile<R>::MINB) void stage_kernel(Params<R> p) {
+__device__ __forceinline__ void stage_tile(const Params<R> p, const int tile) {
   constexpr int TX = Geo<R>::TX, TY = Geo<R>::TY;
-  const int b = blockIdx.x;
-  const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
-  if (tile >= p.n_tiles) return;
   const int tid = threadIdx.x;
   const int i0 = (tile % p.tiles_x) * TX, j0 = (tile / p.tiles_x) * TY;
   const long long n = p.n;
@@ -1013,6 +1013,56 @@ __global__ __launch_bounds__(Geo<R>::NT, Tile<R>::MINB) void stage_kernel(Params
     stage_body<R, STAGE, false>(p, sm, tile, i0, j0, t, dt, t_next);
   else
     stage_body<R, STAGE, true>(p, sm, tile, i0, j0, t, dt, t_next);
+}
+
+// one context: one block per tile, blocks of an XCD on a contiguous band of tiles
+template <typename R, int STAGE>
+__global__ __launch_bounds__(Geo<R>::NT, Tile<R>::MINB) void stage_kernel(Params<R> p) {
+  const int b = blockIdx.x;
+  const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
+  if (tile >= p.n_tiles) return;
+  stage_tile<R, STAGE>(p, tile);
+}
+
+// ---------------------------------------------------------------------------------
+// batched scenarios: one launch per stage over the tiles of every scenario
+// ---------------------------------------------------------------------------------
+constexpr int MAX_BATCH = 256;
+
+// the launch description in device memory: the work list is the scenarios' tiles in
+// order (scenario k owns items start[k] .. start[k+1]-1), and each scenario has its
+// parameters for both buffer phases (its parity flips every step)
+template <typename R>
+struct BatchTable {
+  int n, total, per_xcd, pad;
+  int start[MAX_BATCH + 1];
+  Params<R> p[2][MAX_BATCH];
+};
+
+template <typename R, int STAGE>
+__global__ __launch_bounds__(Geo<R>::NT, Tile<R>::MINB) void stage_kernel_batch(
+    const BatchTable<R>* __restrict__ tab, int phase) {
+  const int b = blockIdx.x;
+  const int g = (b % NXCD) * tab->per_xcd + b / NXCD;
+  if (g >= tab->total) return;
+  int lo = 0, hi = tab->n;  // start[lo] <= g < start[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tab->start[mid] <= g) lo = mid; else hi = mid;
+  }
+  const Params<R> p = tab->p[phase][lo];
+  stage_tile<R, STAGE>(p, g - tab->start[lo]);
+}
+
+// time and health of every scenario of a batch (one thread each)
+template <typename R>
+__global__ void batch_status_kernel(const BatchTable<R>* __restrict__ tab, int phase,
+                                    double* __restrict__ t_out, int* __restrict__ health_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= tab->n) return;
+  const Params<R>& p = tab->p[phase][k];
+  t_out[k] = p.ctrl->t[p.parity];
+  health_out[k] = p.ctrl->health;
 }
 
 // ---------------------------------------------------------------------------------

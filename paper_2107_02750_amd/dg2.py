@@ -21,8 +21,9 @@ MAX_SEGMENTS, MAX_KNOTS = 64, 8192
 SYMBOLS = ("dg2_workspace_size", "dg2_init", "dg2_step", "dg2_run", "dg2_read",
            "dg2_get_scalars", "dg2_next_dt", "dg2_state_bytes", "dg2_get_state",
            "dg2_set_state", "dg2_set_timing", "dg2_get_timing", "dg2_kernel_info",
-           "dg2_bed_info", "dg2_plan_bed_datum", "dg2_tile_grid", "dg2_last_error",
-           "dg2_init_error", "dg2_destroy")
+           "dg2_bed_info", "dg2_plan_bed_datum", "dg2_tile_grid", "dg2_batch_create",
+           "dg2_batch_step", "dg2_batch_run", "dg2_batch_last_error", "dg2_batch_destroy",
+           "dg2_last_error", "dg2_init_error", "dg2_destroy")
 
 _dp = C.POINTER(C.c_double)
 
@@ -82,6 +83,13 @@ def load(path: str = LIB_PATH):
     lib.dg2_init_error.restype = C.c_char_p
     lib.dg2_destroy.argtypes = [vp]
     lib.dg2_destroy.restype = None
+    lib.dg2_batch_create.argtypes = [C.POINTER(vp), i32, i32, C.POINTER(vp)]
+    lib.dg2_batch_step.argtypes = [vp, i32]
+    lib.dg2_batch_run.argtypes = [vp, C.c_double, C.POINTER(i64), C.POINTER(i64)]
+    lib.dg2_batch_last_error.argtypes = [vp]
+    lib.dg2_batch_last_error.restype = C.c_char_p
+    lib.dg2_batch_destroy.argtypes = [vp]
+    lib.dg2_batch_destroy.restype = None
     _lib = lib
     return lib
 
@@ -271,3 +279,44 @@ class DG2:
         self._check(self._lib.dg2_kernel_info(self._h, *[C.byref(x) for x in v]))
         return dict(zip(("tile_x", "tile_y", "threads", "blocks", "lds_bytes"),
                         [x.value for x in v]))
+
+
+class Batch:
+    """Several DG2 simulations of one precision, created on one (non-default) stream,
+    advanced together by shared launches replayed from a HIP graph of graph_steps steps.
+    While the batch exists its members can be read but not stepped alone."""
+
+    def __init__(self, sims, graph_steps: int = 16):
+        lib = load()
+        self._lib = lib
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s._h.value for s in self.sims])
+        h = C.c_void_p()
+        rc = lib.dg2_batch_create(arr, len(self.sims), int(graph_steps), C.byref(h))
+        if rc != 0:
+            raise DG2Error(rc, lib.dg2_batch_last_error(None).decode())
+        self._h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise DG2Error(rc, self._lib.dg2_batch_last_error(self._h).decode())
+
+    def step(self, steps: int = 1) -> None:
+        """steps steps of every member (no host wait)."""
+        self._check(self._lib.dg2_batch_step(self._h, int(steps)))
+
+    def run(self, t_end: float):
+        """Run every member to t_end; returns (steps per member, launch pairs)."""
+        ms = (C.c_int64 * len(self.sims))()
+        lp = C.c_int64()
+        self._check(self._lib.dg2_batch_run(self._h, float(t_end), ms, C.byref(lp)))
+        return [int(x) for x in ms], lp.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.dg2_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

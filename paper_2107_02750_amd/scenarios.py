@@ -174,7 +174,8 @@ def fbm_channel(n: int = 1024, dx: float = 5.0, seed: int = 2, hurst: float = 0.
                 relief: float = 20.0, channel_width: float = 30.0,
                 channel_depth: float = 3.0, amplitude: Optional[float] = None,
                 wavelength: Optional[float] = None, q_peak: float = 50.0,
-                manning: float = 0.035, t_end: float = 7200.0) -> Scenario:
+                manning: float = 0.035, t_end: float = 7200.0,
+                fft_n: Optional[int] = None) -> Scenario:
     """Rugged terrain with a carved meandering channel, initially dry, fed at the west
     edge by a trapezoid hydrograph (0 -> q_peak over 900 s, held to 2700 s, back to 0
     at 3600 s); the other edges are transmissive.
@@ -184,13 +185,13 @@ def fbm_channel(n: int = 1024, dx: float = 5.0, seed: int = 2, hurst: float = 0.
     (from the west) of the terrain along the centreline minus channel_depth, so the
     channel bed never rises downstream. By default the meander has amplitude 500 m and
     wavelength 2000 m on the 1024-cell, 5 m grid, and both scale with the domain length
-    otherwise."""
+    otherwise. fft_n: the spectral grid of the terrain (see fbm_vertices)."""
     if amplitude is None:
         amplitude = 500.0 * n * dx / 5120.0
     if wavelength is None:
         wavelength = 2000.0 * n * dx / 5120.0
     rng = np.random.default_rng(seed + 1000)
-    zv = fbm_vertices(n + 1, seed, hurst, relief)
+    zv = fbm_vertices(n + 1, seed, hurst, relief, fft_n)
     phi = rng.uniform(0.0, 2.0 * np.pi)
     xv = np.arange(n + 1) * dx
     yv = np.arange(n + 1) * dx
@@ -221,6 +222,26 @@ def fbm_channel_wet(n: int = 1024, dx: float = 5.0, seed: int = 2, eta: float = 
     vert = np.stack([depth, np.full_like(depth, qx), np.zeros_like(depth)])
     return Scenario("fbm_channel_wet", n, n, dx, base.zv, MODE_VERTEX, vert,
                     manning_scalar=manning, t_end=600.0)
+
+
+def batch_scenarios(count: int = 64, seed: int = 400, side_lo: int = 256, side_hi: int = 1024,
+                    t_end: float = 1800.0) -> list:
+    """Independent flood scenarios of uneven size for batched runs: scenario k has a
+    square grid of side ~ U{side_lo..side_hi} cells, dx ~ U[2, 10] m, fBm channel
+    terrain of seed seed + k, Manning n ~ U(0.015, 0.06) and a trapezoid inflow
+    hydrograph peaking at ~ U(5, 100) m^3/s."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n = int(rng.integers(side_lo, side_hi + 1))
+        dx = float(rng.uniform(2.0, 10.0))
+        man = float(rng.uniform(0.015, 0.06))
+        qp = float(rng.uniform(5.0, 100.0))
+        fft_n = 1 << int(np.ceil(np.log2(n + 1)))  # a period beyond the grid is enough
+        sc = fbm_channel(n=n, dx=dx, seed=seed + k, manning=man, q_peak=qp, t_end=t_end,
+                         fft_n=fft_n)
+        out.append(dataclasses.replace(sc, name=f"batch{k}_{n}"))
+    return out
 
 
 def urban_blocks(n: int = 2048, dx: float = 2.0, seed: int = 3, n_blocks: int = 4000,
