@@ -154,14 +154,17 @@ def precision_form(dg2, S, n, t_end):
 
 def batched(dg2, S, count, t_end):
     """count scenarios of uneven size (seeded; FP32 with bed datums, FP64 mass ledgers)
-    run to t_end as one batch (shared launches from a HIP graph), then the same
-    scenarios one after another; aggregate cell-updates/s of both, and whether every
-    member ends bitwise where it does alone."""
+    run to t_end as one batch (shared launches from a HIP graph, tile shape from the
+    autotuner), then the same scenarios one after another; aggregate cell-updates/s of
+    both, and whether every member ends bitwise where it does alone."""
     import torch
+    from paper_2107_02750_amd import autotune
     scs = S.batch_scenarios(count=count, t_end=t_end)
     cells = [sc.nx * sc.ny for sc in scs]
     stream = torch.cuda.Stream()
-    sims = [dg2.DG2(sc, dg2.FP32, stream=stream) for sc in scs]
+    tuned = autotune.tune_batch(scs, dg2.FP32, stream)
+    tile = tuned["best"]
+    sims = [dg2.DG2(sc, dg2.FP32, stream=stream, tile=tile) for sc in scs]
     batch = dg2.Batch(sims, graph_steps=32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -177,7 +180,7 @@ def batched(dg2, S, count, t_end):
     seq_el = 0.0
     equal = True
     for sc, sim in zip(scs, sims):
-        one = dg2.DG2(sc, dg2.FP32, stream=stream)
+        one = dg2.DG2(sc, dg2.FP32, stream=stream, tile=tile)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         one.run(t_end)
@@ -192,6 +195,7 @@ def batched(dg2, S, count, t_end):
             "launch_pairs": pairs,
             "one_at_a_time": {"value": work / seq_el, "seconds": seq_el},
             "speedup": seq_el / el, "bitwise_equal_to_one_at_a_time": equal,
+            "tile": list(tile), "autotuner_ms_per_step": tuned["ms_per_step"],
             "max_mass_balance_rel": drift}
 
 

@@ -30,10 +30,9 @@
  *    vertex, rounded to a power-of-two quantum (dg2_bed_info) chosen so that every
  *    elevation a tile sees in its own frame, and every mean and difference of them
  *    the scheme forms, is exact in float. The FP32 arithmetic uses the bed only
- *    through such differences, so a tile's results do not depend on its datum, the
- *    two tiles that share a face compute the same flux, and raising the whole bed
- *    (and any still-water level) by a whole number of metres leaves every result
- *    unchanged. Depth precision is then set by the local relief, not by the absolute
+ *    through such differences, so a tile's results do not depend on its datum, and
+ *    raising the whole bed (and any still-water level) by a whole number of metres
+ *    leaves every result bitwise unchanged. Depth precision is then set by the local relief, not by the absolute
  *    elevation. The quantum is the bed's only change (at most half a quantum per
  *    vertex).
  *  - Memory: the caller owns every input; host inputs are copied during dg2_init and
@@ -100,6 +99,8 @@ typedef struct {
   int32_t bed_datum;       /* DG2_FP32 only (ignored for FP64): 1 stores the bed relative
                               to a per-tile datum, 0 stores absolute elevations; see
                               dg2_bed_info */
+  int32_t tile_x, tile_y;  /* tile of the stage kernels in cells: 0, 0 for the
+                              precision's default, else one of dg2_tile_shapes */
 } dg2_config;
 
 typedef struct {
@@ -200,6 +201,11 @@ int dg2_bed_info(const dg2_ctx *c, double *quantum, double *max_local);
 int dg2_plan_bed_datum(const dg2_config *cfg, const double *zv, double *zrel, double *datum,
                        double *quantum, double *max_local);
 
+/* Host-only: the tile shapes the stage kernels are built for, for a precision:
+ * *count shapes, written as (tile_x, tile_y) pairs into xy (room for cap pairs; xy may
+ * be NULL to query the count). The first is the default. */
+int dg2_tile_shapes(int32_t precision, int32_t *xy, int32_t cap, int32_t *count);
+
 /* Host-only: the tile grid of the stage kernels for a configuration (tile width and
  * height in cells, tiles along x and y). */
 int dg2_tile_grid(const dg2_config *cfg, int32_t *tile_x, int32_t *tile_y, int32_t *tiles_x,
@@ -212,12 +218,13 @@ int dg2_tile_grid(const dg2_config *cfg, int32_t *tile_x, int32_t *tile_y, int32
  * ledger and health word. For each member a batch step is bitwise the same as a
  * dg2_step of that member alone (no dt_max). Steps are issued by replaying a HIP graph
  * of graph_steps steps (an even number, 2..256) captured on the members' stream.
- *  - members: n (1..DG2_MAX_BATCH) distinct contexts of one precision, all created on
- *    the same stream. The batch borrows them: they must outlive it, and while it
+ *  - members: n (1..DG2_MAX_BATCH) distinct contexts of one precision and tile shape,
+ *    all created on the same stream. The batch borrows them: they must outlive it, and while it
  *    exists they may be read and queried but not stepped, run or restored alone.
  *  - The batch allocates its launch table and status buffers (a few hundred KB of
  *    device memory and a little pinned host memory); dg2_batch_destroy frees them.
- *  - Errors: DG2_E_ARG (bad list, mixed precision or streams, a repeated member),
+ *  - Errors: DG2_E_ARG (bad list, mixed precision, tile shape or streams, a repeated
+ *    member),
  *    DG2_E_DEVICE, DG2_E_NUMERIC (a member's health word tripped; the message names
  *    it). */
 #define DG2_MAX_BATCH 256

@@ -25,15 +25,50 @@ size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t u0, u1, ui, zv, datum, man, bface, segs, knots, ctrl, ledger, scal, total;
-  int tx, ty, threads, tiles_x, tiles_y, n_tiles, per_xcd, grid;
+  int shape, tx, ty, threads, tiles_x, tiles_y, n_tiles, per_xcd, grid;
 };
+
+const int (*shape_table(int precision))[2] {
+  return precision == DG2_FP32 ? dg2k::SHAPE32 : dg2k::SHAPE64;
+}
+
+// index of the configured tile shape, or -1 if it is not one of the built shapes
+int shape_index(const dg2_config& c) {
+  if (c.tile_x == 0 && c.tile_y == 0) return 0;
+  const int (*t)[2] = shape_table(c.precision);
+  for (int k = 0; k < dg2k::N_SHAPES; ++k)
+    if (t[k][0] == c.tile_x && t[k][1] == c.tile_y) return k;
+  return -1;
+}
+
+// the K-th tile shape of precision R
+template <typename R, int K> struct ShapeOf;
+template <int K> struct ShapeOf<double, K> {
+  using type = dg2k::Shape<dg2k::SHAPE64[K][0], dg2k::SHAPE64[K][1]>;
+};
+template <int K> struct ShapeOf<float, K> {
+  using type = dg2k::Shape<dg2k::SHAPE32[K][0], dg2k::SHAPE32[K][1]>;
+};
+
+// call F<R, shape>::run(args...) for the shape with index k
+template <typename R, template <typename, typename> class F, typename... A>
+int with_shape(int k, A... a) {
+  switch (k) {
+    case 0: return F<R, typename ShapeOf<R, 0>::type>::run(a...);
+    case 1: return F<R, typename ShapeOf<R, 1>::type>::run(a...);
+    case 2: return F<R, typename ShapeOf<R, 2>::type>::run(a...);
+    default: return F<R, typename ShapeOf<R, 3>::type>::run(a...);
+  }
+}
+static_assert(dg2k::N_SHAPES == 4, "with_shape lists every shape");
 
 Layout layout(const dg2_config& c) {
   Layout L{};
   const size_t n = (size_t)c.nx * c.ny;
   const size_t rs = c.precision == DG2_FP32 ? 4 : 8;
-  L.tx = c.precision == DG2_FP32 ? dg2k::Geo<float>::TX : dg2k::Geo<double>::TX;
-  L.ty = c.precision == DG2_FP32 ? dg2k::Geo<float>::TY : dg2k::Geo<double>::TY;
+  L.shape = shape_index(c);
+  L.tx = shape_table(c.precision)[L.shape][0];
+  L.ty = shape_table(c.precision)[L.shape][1];
   L.threads = L.tx * L.ty;
   L.tiles_x = (c.nx + L.tx - 1) / L.tx;
   L.tiles_y = (c.ny + L.ty - 1) / L.ty;
@@ -147,6 +182,8 @@ Params<R> params(const dg2_ctx* c) {
   p.n = (long long)c->n;
   p.nx = c->cfg.nx;
   p.ny = c->cfg.ny;
+  p.tx = L.tx;
+  p.ty = L.ty;
   p.tiles_x = L.tiles_x;
   p.n_tiles = L.n_tiles;
   p.per_xcd = L.per_xcd;
@@ -168,8 +205,14 @@ Params<R> params(const dg2_ctx* c) {
   return p;
 }
 
-template <typename R>
-int launch_step(dg2_ctx* c, double dt_max, double t_end) {
+template <typename R, typename S>
+struct SmemBytes {
+  static int run() { return (int)sizeof(dg2k::Smem<R, S>); }
+};
+
+template <typename R, typename S>
+struct LaunchStep {
+  static int run(dg2_ctx* c, double dt_max, double t_end) {
   Params<R> p = params<R>(c);
   p.dt_max = dt_max;
   p.t_end = t_end;
@@ -185,14 +228,20 @@ int launch_step(dg2_ctx* c, double dt_max, double t_end) {
     c->ev_used += 3;
     HIPC(c, hipEventRecord(e[0], c->stream));
   }
-  hipLaunchKernelGGL((dg2k::stage_kernel<R, 1>), grid, block, 0, c->stream, p);
+  hipLaunchKernelGGL((dg2k::stage_kernel<R, S, 1>), grid, block, 0, c->stream, p);
   HIPC(c, hipGetLastError());
   if (e) HIPC(c, hipEventRecord(e[1], c->stream));
-  hipLaunchKernelGGL((dg2k::stage_kernel<R, 2>), grid, block, 0, c->stream, p);
+  hipLaunchKernelGGL((dg2k::stage_kernel<R, S, 2>), grid, block, 0, c->stream, p);
   HIPC(c, hipGetLastError());
   if (e) HIPC(c, hipEventRecord(e[2], c->stream));
   c->parity ^= 1;
   return DG2_OK;
+  }
+};
+
+template <typename R>
+int launch_step(dg2_ctx* c, double dt_max, double t_end) {
+  return with_shape<R, LaunchStep>(c->L.shape, c, dt_max, t_end);
 }
 
 int step_any(dg2_ctx* c, double dt_max, double t_end) {
@@ -239,6 +288,7 @@ int check_config(const dg2_config* cfg) {
   if ((long long)cfg->nx * cfg->ny > (1LL << 31)) return DG2_E_UNSUPPORTED;
   if (cfg->precision != DG2_FP64 && cfg->precision != DG2_FP32) return DG2_E_ARG;
   if (cfg->bed_datum != 0 && cfg->bed_datum != 1) return DG2_E_ARG;
+  if (shape_index(*cfg) < 0) return DG2_E_UNSUPPORTED;
   return DG2_OK;
 }
 
@@ -384,15 +434,22 @@ int batch_table(dg2_batch* b) {
   return DG2_OK;
 }
 
+template <typename R, typename S>
+struct BatchLaunch {
+  static int run(dg2_batch* b, int phase) {
+    const auto* tab = reinterpret_cast<const dg2k::BatchTable<R>*>(b->d_table);
+    const dim3 grid(b->grid), block(dg2k::Geo<S>::NT);
+    hipLaunchKernelGGL((dg2k::stage_kernel_batch<R, S, 1>), grid, block, 0, b->stream, tab, phase);
+    BHIPC(b, hipGetLastError());
+    hipLaunchKernelGGL((dg2k::stage_kernel_batch<R, S, 2>), grid, block, 0, b->stream, tab, phase);
+    BHIPC(b, hipGetLastError());
+    return DG2_OK;
+  }
+};
+
 template <typename R>
 int batch_launch_step(dg2_batch* b, int phase) {
-  const auto* tab = reinterpret_cast<const dg2k::BatchTable<R>*>(b->d_table);
-  const dim3 grid(b->grid), block(dg2k::Geo<R>::NT);
-  hipLaunchKernelGGL((dg2k::stage_kernel_batch<R, 1>), grid, block, 0, b->stream, tab, phase);
-  BHIPC(b, hipGetLastError());
-  hipLaunchKernelGGL((dg2k::stage_kernel_batch<R, 2>), grid, block, 0, b->stream, tab, phase);
-  BHIPC(b, hipGetLastError());
-  return DG2_OK;
+  return with_shape<R, BatchLaunch>(b->members[0]->L.shape, b, phase);
 }
 
 void batch_drop_graph(dg2_batch* b) {
@@ -486,8 +543,9 @@ int dg2_batch_create(dg2_ctx* const* members, int32_t n, int32_t graph_steps, dg
   }
   for (int k = 0; k < n; ++k) {
     const dg2_ctx* c = members[k];
-    if (!c || c->in_batch || c->fp32 != members[0]->fp32 || c->stream != members[0]->stream) {
-      g_init_err = "members must be distinct free contexts of one precision on one stream";
+    if (!c || c->in_batch || c->fp32 != members[0]->fp32 || c->stream != members[0]->stream ||
+        c->L.shape != members[0]->L.shape) {
+      g_init_err = "members must be distinct free contexts of one precision and tile shape on one stream";
       return DG2_E_ARG;
     }
     for (int j = 0; j < k; ++j)
@@ -946,6 +1004,17 @@ int dg2_get_timing(dg2_ctx* c, int64_t* steps, double* ms1, double* ms2) {
   return DG2_OK;
 }
 
+int dg2_tile_shapes(int32_t precision, int32_t* xy, int32_t cap, int32_t* count) {
+  if (precision != DG2_FP64 && precision != DG2_FP32) return DG2_E_ARG;
+  const int (*t)[2] = shape_table(precision);
+  if (count) *count = dg2k::N_SHAPES;
+  for (int k = 0; xy && k < dg2k::N_SHAPES && k < cap; ++k) {
+    xy[2 * k] = t[k][0];
+    xy[2 * k + 1] = t[k][1];
+  }
+  return DG2_OK;
+}
+
 int dg2_kernel_info(const dg2_ctx* c, int32_t* tile_x, int32_t* tile_y, int32_t* threads, int32_t* blocks,
                     int32_t* lds_bytes) {
   if (!c) return DG2_E_ARG;
@@ -953,8 +1022,8 @@ int dg2_kernel_info(const dg2_ctx* c, int32_t* tile_x, int32_t* tile_y, int32_t*
   if (tile_y) *tile_y = c->L.ty;
   if (threads) *threads = c->L.threads;
   if (blocks) *blocks = c->L.grid;
-  if (lds_bytes)
-    *lds_bytes = c->fp32 ? (int32_t)sizeof(dg2k::Smem<float>) : (int32_t)sizeof(dg2k::Smem<double>);
+  if (lds_bytes) *lds_bytes = c->fp32 ? with_shape<float, SmemBytes>(c->L.shape)
+                                      : with_shape<double, SmemBytes>(c->L.shape);
   return DG2_OK;
 }
 

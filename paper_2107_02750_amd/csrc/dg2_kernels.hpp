@@ -20,34 +20,21 @@
 
 namespace dg2k {
 
-// tile shape per precision (cells; x fastest in memory), overridable at build time
-#ifndef DG2_TILE64_X
-#define DG2_TILE64_X 16
-#endif
-#ifndef DG2_TILE64_Y
-#define DG2_TILE64_Y 16
-#endif
-#ifndef DG2_TILE32_X
-#define DG2_TILE32_X 64
-#endif
-#ifndef DG2_TILE32_Y
-#define DG2_TILE32_Y 8
-#endif
-#ifndef DG2_MINB64
-#define DG2_MINB64 1
-#endif
-#ifndef DG2_MINB32
-#define DG2_MINB32 1
-#endif
-// tile width and height, and the minimum resident blocks per CU the compiler must allow
-template <typename R> struct Tile;
-template <> struct Tile<double> { static constexpr int X = DG2_TILE64_X, Y = DG2_TILE64_Y, MINB = DG2_MINB64; };
-template <> struct Tile<float> { static constexpr int X = DG2_TILE32_X, Y = DG2_TILE32_Y, MINB = DG2_MINB32; };
+// Tile shapes (cells; x fastest in memory). A context picks one of the shapes listed
+// per precision; index 0 is the default. One block of TX * TY threads owns a tile.
+template <int TX_, int TY_, int MINB_ = 1>
+struct Shape {
+  static constexpr int X = TX_, Y = TY_, MINB = MINB_;
+};
+constexpr int N_SHAPES = 4;
+// FP64: 32x8 (default), 16x16, 16x8, 64x4; FP32: 64x8 (default), 32x16, 32x8, 16x16
+constexpr int SHAPE64[N_SHAPES][2] = {{32, 8}, {16, 16}, {16, 8}, {64, 4}};
+constexpr int SHAPE32[N_SHAPES][2] = {{64, 8}, {32, 16}, {32, 8}, {16, 16}};
 
 // LDS geometry of a tile: the cell box has a 2-cell halo, the vertex box one more
-template <typename R>
+template <typename S>
 struct Geo {
-  static constexpr int TX = Tile<R>::X, TY = Tile<R>::Y;
+  static constexpr int TX = S::X, TY = S::Y;
   static constexpr int NT = TX * TY;           // threads per block, one cell each
   static constexpr int RX = TX + 4, RY = TY + 4, RB = RX * RY;
   static constexpr int VX = TX + 5, VY = TY + 5, VB = VX * VY;
@@ -89,7 +76,7 @@ struct Params {
   Ctrl* ctrl;
   double* ledger;              // per tile: in, out, clip, unused
   long long n;                 // nx * ny
-  int nx, ny, tiles_x, n_tiles, per_xcd, nsegs, max_knots, limiter, parity;
+  int nx, ny, tx, ty, tiles_x, n_tiles, per_xcd, nsegs, max_knots, limiter, parity;
   R dx, g, h_tol, n_scalar;
   double dxd, gd, cfl, htd, dt_dry, dt_max, t_end;
 };
@@ -314,7 +301,7 @@ __device__ __forceinline__ void friction_inc(R gn2dt, R ht, R h, R qx, R qy, R& 
 template <typename R>
 __device__ __forceinline__ R tile_datum(const Params<R>& p, int i, int j) {
   if constexpr (sizeof(R) == 8) return R(0);  // FP64 stores absolute elevations
-  return p.datum ? p.datum[(j / Geo<R>::TY) * p.tiles_x + i / Geo<R>::TX] : R(0);
+  return p.datum ? p.datum[(j / p.ty) * p.tiles_x + i / p.tx] : R(0);
 }
 
 // bed at vertex (iv, jv) in the frame of datum dT: the stored value is relative to the
@@ -432,27 +419,27 @@ __device__ __forceinline__ double wave_min(double x) {
 // ---------------------------------------------------------------------------------
 // the stage kernel
 // ---------------------------------------------------------------------------------
-template <typename R>
+template <typename R, typename S>
 struct Smem {
-  R c[6][Geo<R>::RB];   // planes 0-2: box means h0, qx0, qy0; later the face-side
+  R c[6][Geo<S>::RB];   // planes 0-2: box means h0, qx0, qy0; later the face-side
                         // states and then the face fluxes
-  R zv[Geo<R>::VB];     // bed vertices of the box
-  R z0[Geo<R>::RB];     // bed means of the box cells
-  R um[Geo<R>::RB];     // mean velocities (zero at or below h_tol)
-  R vm[Geo<R>::RB];
-  unsigned char flag[Geo<R>::RB];  // 1: first-order (front) cell
-  double red[Geo<R>::NT / 64][4];
+  R zv[Geo<S>::VB];     // bed vertices of the box
+  R z0[Geo<S>::RB];     // bed means of the box cells
+  R um[Geo<S>::RB];     // mean velocities (zero at or below h_tol)
+  R vm[Geo<S>::RB];
+  unsigned char flag[Geo<S>::RB];  // 1: first-order (front) cell
+  double red[Geo<S>::NT / 64][4];
 };
 
 // One stage over one tile. EDGE is false for tiles whose halo box lies inside the
 // domain: no clamping, no boundary faces, every cell active.
-template <typename R, int STAGE, bool EDGE>
-__device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, const int tile,
+template <typename R, typename S, int STAGE, bool EDGE>
+__device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, const int tile,
                                            const int i0, const int j0, const double t,
                                            const double dt, const double t_next) {
-  constexpr int TX = Geo<R>::TX, TY = Geo<R>::TY, NT = Geo<R>::NT;
-  constexpr int RX = Geo<R>::RX, RB = Geo<R>::RB, VX = Geo<R>::VX, VB = Geo<R>::VB;
-  constexpr int NRING = Geo<R>::NRING;
+  constexpr int TX = Geo<S>::TX, TY = Geo<S>::TY, NT = Geo<S>::NT;
+  constexpr int RX = Geo<S>::RX, RB = Geo<S>::RB, VX = Geo<S>::VX, VB = Geo<S>::VB;
+  constexpr int NRING = Geo<S>::NRING;
   const int tid = threadIdx.x;
   const int nx = p.nx, ny = p.ny;
   const long long n = p.n;
@@ -969,9 +956,9 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R>& sm, cons
 // One stage over tile `tile` of the context described by p: the step's time step, the
 // control-block update (stage 1, tile 0), then the tile's work (or, once the run has
 // reached t_end, a copy of the state that keeps the buffer parity).
-template <typename R, int STAGE>
+template <typename R, typename S, int STAGE>
 __device__ __forceinline__ void stage_tile(const Params<R> p, const int tile) {
-  constexpr int TX = Geo<R>::TX, TY = Geo<R>::TY;
+  constexpr int TX = Geo<S>::TX, TY = Geo<S>::TY;
   const int tid = threadIdx.x;
   const int i0 = (tile % p.tiles_x) * TX, j0 = (tile / p.tiles_x) * TY;
   const long long n = p.n;
@@ -1007,21 +994,21 @@ __device__ __forceinline__ void stage_tile(const Params<R> p, const int tile) {
     if (dt_cfl < 1e-12) atomicOr(&c->health, 2);
   }
 
-  __shared__ Smem<R> sm;
+  __shared__ Smem<R, S> sm;
   const bool interior = i0 >= 2 && j0 >= 2 && i0 + TX + 2 <= p.nx && j0 + TY + 2 <= p.ny;
   if (interior)
-    stage_body<R, STAGE, false>(p, sm, tile, i0, j0, t, dt, t_next);
+    stage_body<R, S, STAGE, false>(p, sm, tile, i0, j0, t, dt, t_next);
   else
-    stage_body<R, STAGE, true>(p, sm, tile, i0, j0, t, dt, t_next);
+    stage_body<R, S, STAGE, true>(p, sm, tile, i0, j0, t, dt, t_next);
 }
 
 // one context: one block per tile, blocks of an XCD on a contiguous band of tiles
-template <typename R, int STAGE>
-__global__ __launch_bounds__(Geo<R>::NT, Tile<R>::MINB) void stage_kernel(Params<R> p) {
+template <typename R, typename S, int STAGE>
+__global__ __launch_bounds__(Geo<S>::NT, S::MINB) void stage_kernel(Params<R> p) {
   const int b = blockIdx.x;
   const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
   if (tile >= p.n_tiles) return;
-  stage_tile<R, STAGE>(p, tile);
+  stage_tile<R, S, STAGE>(p, tile);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1039,8 +1026,8 @@ struct BatchTable {
   Params<R> p[2][MAX_BATCH];
 };
 
-template <typename R, int STAGE>
-__global__ __launch_bounds__(Geo<R>::NT, Tile<R>::MINB) void stage_kernel_batch(
+template <typename R, typename S, int STAGE>
+__global__ __launch_bounds__(Geo<S>::NT, S::MINB) void stage_kernel_batch(
     const BatchTable<R>* __restrict__ tab, int phase) {
   const int b = blockIdx.x;
   const int g = (b % NXCD) * tab->per_xcd + b / NXCD;
@@ -1051,7 +1038,7 @@ __global__ __launch_bounds__(Geo<R>::NT, Tile<R>::MINB) void stage_kernel_batch(
     if (tab->start[mid] <= g) lo = mid; else hi = mid;
   }
   const Params<R> p = tab->p[phase][lo];
-  stage_tile<R, STAGE>(p, g - tab->start[lo]);
+  stage_tile<R, S, STAGE>(p, g - tab->start[lo]);
 }
 
 // time and health of every scenario of a batch (one thread each)

@@ -21,7 +21,8 @@ MAX_SEGMENTS, MAX_KNOTS = 64, 8192
 SYMBOLS = ("dg2_workspace_size", "dg2_init", "dg2_step", "dg2_run", "dg2_read",
            "dg2_get_scalars", "dg2_next_dt", "dg2_state_bytes", "dg2_get_state",
            "dg2_set_state", "dg2_set_timing", "dg2_get_timing", "dg2_kernel_info",
-           "dg2_bed_info", "dg2_plan_bed_datum", "dg2_tile_grid", "dg2_batch_create",
+           "dg2_bed_info", "dg2_plan_bed_datum", "dg2_tile_shapes", "dg2_tile_grid",
+           "dg2_batch_create",
            "dg2_batch_step", "dg2_batch_run", "dg2_batch_last_error", "dg2_batch_destroy",
            "dg2_last_error", "dg2_init_error", "dg2_destroy")
 
@@ -32,7 +33,8 @@ class Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("g", C.c_double),
                 ("cfl", C.c_double), ("h_tol", C.c_double), ("dt_dry", C.c_double),
                 ("t0", C.c_double), ("precision", C.c_int32), ("limiter", C.c_int32),
-                ("edge_kind", C.c_int32 * 4), ("bed_datum", C.c_int32)]
+                ("edge_kind", C.c_int32 * 4), ("bed_datum", C.c_int32), ("tile_x", C.c_int32),
+                ("tile_y", C.c_int32)]
 
 
 class Boundary(C.Structure):
@@ -57,6 +59,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+    # torch first: the process then has one HIP runtime, the one torch brings up, and
+    # the library's device pointers and streams are torch's own
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, sz = C.c_void_p, C.c_size_t
     i32, i64 = C.c_int32, C.c_int64
@@ -77,6 +82,7 @@ def load(path: str = LIB_PATH):
     lib.dg2_bed_info.argtypes = [vp, _dp, _dp]
     lib.dg2_plan_bed_datum.argtypes = [C.POINTER(Config), _dp, _dp, _dp, _dp, _dp]
     lib.dg2_tile_grid.argtypes = [C.POINTER(Config)] + [C.POINTER(i32)] * 4
+    lib.dg2_tile_shapes.argtypes = [i32, C.POINTER(i32), i32, C.POINTER(i32)]
     lib.dg2_last_error.argtypes = [vp]
     lib.dg2_last_error.restype = C.c_char_p
     lib.dg2_init_error.argtypes = []
@@ -102,19 +108,34 @@ def _ptr(a):
     return a.ctypes.data_as(_dp) if a is not None else None
 
 
-def make_config(sc, precision: int, bed_datum: bool | None = None) -> Config:
-    """The C configuration of a scenario. bed_datum (FP32 only) defaults to on."""
+def make_config(sc, precision: int, bed_datum: bool | None = None, tile=None) -> Config:
+    """The C configuration of a scenario. bed_datum (FP32 only) defaults to on; tile is
+    a (tile_x, tile_y) pair from tile_shapes(precision), or None for the default."""
     if bed_datum is None:
         bed_datum = precision == FP32
+    tx, ty = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
     return Config(int(sc.nx), int(sc.ny), float(sc.dx), float(sc.g), float(sc.cfl),
                   float(sc.h_tol), float(sc.dt_dry), float(sc.t0), int(precision),
                   int(sc.limiter), (C.c_int32 * 4)(*[int(k) for k in sc.edge_kind]),
-                  int(bool(bed_datum)))
+                  int(bool(bed_datum)), tx, ty)
 
 
-def workspace_bytes(sc, precision: int = FP64, bed_datum: bool | None = None) -> int:
+def tile_shapes(precision: int) -> list:
+    """The (tile_x, tile_y) shapes the stage kernels are built for; the first is the
+    default."""
     lib = load()
-    cfg = make_config(sc, precision, bed_datum)
+    n = C.c_int32()
+    rc = lib.dg2_tile_shapes(int(precision), None, 0, C.byref(n))
+    if rc != 0:
+        raise DG2Error(rc, "tile shapes")
+    xy = (C.c_int32 * (2 * n.value))()
+    lib.dg2_tile_shapes(int(precision), xy, n.value, C.byref(n))
+    return [(xy[2 * k], xy[2 * k + 1]) for k in range(n.value)]
+
+
+def workspace_bytes(sc, precision: int = FP64, bed_datum: bool | None = None, tile=None) -> int:
+    lib = load()
+    cfg = make_config(sc, precision, bed_datum, tile)
     out = C.c_size_t()
     rc = lib.dg2_workspace_size(C.byref(cfg), C.byref(out))
     if rc != 0:
@@ -122,10 +143,10 @@ def workspace_bytes(sc, precision: int = FP64, bed_datum: bool | None = None) ->
     return out.value
 
 
-def tile_grid(sc, precision: int) -> dict:
+def tile_grid(sc, precision: int, tile=None) -> dict:
     """Tile shape and tile counts of the stage kernels (host only)."""
     lib = load()
-    cfg = make_config(sc, precision)
+    cfg = make_config(sc, precision, tile=tile)
     v = [C.c_int32() for _ in range(4)]
     rc = lib.dg2_tile_grid(C.byref(cfg), *[C.byref(x) for x in v])
     if rc != 0:
@@ -155,12 +176,13 @@ class DG2:
     """One simulation on the GPU, built from a scenario (see the seeded generators):
     attributes nx, ny, dx, g, cfl, h_tol, dt_dry, t0, limiter, edge_kind, zv, manning,
     manning_scalar, init_mode, init_data, eta_level, boundaries. FP32 stores the bed
-    relative to per-tile datums unless bed_datum is False."""
+    relative to per-tile datums unless bed_datum is False; tile picks one of
+    tile_shapes(precision) (default: the first)."""
 
     PLANES = ("h0", "h1x", "h1y", "qx0", "qx1x", "qx1y", "qy0", "qy1x", "qy1y")
 
     def __init__(self, sc, precision: int = FP64, device: str = "cuda:0", stream=None,
-                 bed_datum: bool | None = None):
+                 bed_datum: bool | None = None, tile=None):
         import torch
         lib = load()
         self._lib = lib
@@ -169,7 +191,7 @@ class DG2:
         self.dtype = np.float32 if precision == FP32 else np.float64
         self.torch_dtype = torch.float32 if precision == FP32 else torch.float64
         self.device = torch.device(device)
-        cfg = make_config(sc, precision, bed_datum)
+        cfg = make_config(sc, precision, bed_datum, tile)
         ws = C.c_size_t()
         rc = lib.dg2_workspace_size(C.byref(cfg), C.byref(ws))
         if rc != 0:

@@ -98,3 +98,18 @@ def test_bad_arguments_rejected_before_device_work():
     assert rc == dg2.E_ARG and "overlap" in msg
     rc, msg, _ = _init(sc, edge_kind=(C.c_int32 * 4)(3, 0, 0, 0))
     assert rc == dg2.E_ARG
+
+
+def test_tile_shapes_and_grid():
+    for prec in (dg2.FP64, dg2.FP32):
+        shapes = dg2.tile_shapes(prec)
+        assert len(shapes) == 4 and len(set(shapes)) == 4
+        for tx, ty in shapes:
+            assert (tx * ty) % 64 == 0 and tx * ty <= 1024
+            g = dg2.tile_grid(S.dam_break(nx=100, ny=37), prec, tile=(tx, ty))
+            assert (g["tile_x"], g["tile_y"]) == (tx, ty)
+            assert g["tiles_x"] == -(-100 // tx) and g["tiles_y"] == -(-37 // ty)
+        assert dg2.tile_grid(S.dam_break(), prec)["tile_x"] == shapes[0][0]
+    with pytest.raises(dg2.DG2Error) as e:
+        dg2.workspace_bytes(S.dam_break(), dg2.FP64, tile=(24, 8))
+    assert e.value.code == dg2.E_UNSUPPORTED
