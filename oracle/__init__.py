@@ -1,7 +1,8 @@
 """ctypes wrapper of the FP64 CPU oracle (oracle/libdg2ref.so).
 
 TEST INFRASTRUCTURE ONLY: the plain, slow reference for the uniform-grid DG2 step of
-arXiv:2107.02750 (Sect. 2.1.1, 2.1.4) that the GPU library is checked against. Only the
+arXiv:2107.02750 (Sect. 2.1.1, 2.1.4), and for its FV1 counterpart (Sect. 2.1.2),
+that the GPU library is checked against. Only the
 test suite, the package smoke check and the benchmark's CPU-baseline leg may use it.
 
 Inputs are passed as plain arrays (a scenario object from the seeded generators supplies
@@ -23,7 +24,8 @@ _dp = C.POINTER(C.c_double)
 class _Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("g", C.c_double),
                 ("cfl", C.c_double), ("h_tol", C.c_double), ("dt_dry", C.c_double),
-                ("t0", C.c_double), ("limiter", C.c_int32), ("edge_kind", C.c_int32 * 4)]
+                ("t0", C.c_double), ("limiter", C.c_int32), ("edge_kind", C.c_int32 * 4),
+                ("scheme", C.c_int32)]
 
 
 class _Boundary(C.Structure):
@@ -99,7 +101,8 @@ class Oracle:
         self._lib = lib
         self.nx, self.ny = int(sc.nx), int(sc.ny)
         cfg = _Config(self.nx, self.ny, sc.dx, sc.g, sc.cfl, sc.h_tol, sc.dt_dry, sc.t0,
-                      int(sc.limiter), (C.c_int32 * 4)(*sc.edge_kind))
+                      int(sc.limiter), (C.c_int32 * 4)(*sc.edge_kind),
+                      int(getattr(sc, "scheme", 0)))
         self._keep = []
         zv = _f64(sc.zv)
         man = _f64(sc.manning)

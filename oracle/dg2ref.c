@@ -703,9 +703,142 @@ static int do_step(dg2ref_ctx *c, double dt_max, double t_end, double *dt_used) 
   return DG2REF_OK;
 }
 
+/* ------------------------------------------------------------------------------ */
+/* FV1 (Sect. 2.1.2, eq 5-7): h, qx, qy and the bed are constant per cell (the      */
+/* means; the bed is z0 of eq 8). The operator keeps only L0, built from the HLL     */
+/* fluxes of the two cell means at each face, and eq 7 advances the means by one     */
+/* forward-Euler step with Courant number 0.5. Friction is applied first, at the    */
+/* cell centre, as in DG2. Reading: the faces get the same temporary revision as    */
+/* DG2 (here with the two cells' own flat beds: z* = max, h* = max(0, eta - z*),    */
+/* per-side z** = min(z*, eta)) and the bed source of L0 in its FV1 form,           */
+/* -g (hE* + hW*)/2 (zE** - zW**)/dx, which keeps still water still exactly.        */
+/* ------------------------------------------------------------------------------ */
+static void fv1_faces(dg2ref_ctx *c, const double *S, double t, double *in_rate,
+                      double *out_rate) {
+  const int nx = c->nx, ny = c->ny;
+  const size_t n = c->n;
+  const double g = c->cfg.g, ht = c->cfg.h_tol;
+  const double *h = S + PL(0, 0) * n, *qx = S + PL(1, 0) * n, *qy = S + PL(2, 0) * n;
+  for (int j = 0; j < ny; ++j)
+    for (int f = 0; f <= nx; ++f) {
+      face_t *fc = &c->xf[(size_t)j * (nx + 1) + f];
+      size_t kl = (size_t)j * nx + (f - 1), kr = (size_t)j * nx + f;
+      double zl = f > 0 ? c->z0[kl] : c->z0[kr];
+      double zr = f < nx ? c->z0[kr] : c->z0[kl];
+      double zs = zl > zr ? zl : zr;
+      if (f > 0) fc->lo = revise(h[kl], qx[kl], qy[kl], zl, zs, ht);
+      if (f < nx) fc->hi = revise(h[kr], qx[kr], qy[kr], zr, zs, ht);
+      double gh, gu, gv;
+      if (f == 0) {
+        ghost(c, &c->bw[j], t, 1, 1.0, fc->hi.h, fc->hi.u, fc->hi.v, &gh, &gu, &gv);
+        fc->lo.h = gh; fc->lo.u = gu; fc->lo.v = gv; fc->lo.z = zs;
+      } else if (f == nx) {
+        ghost(c, &c->be[j], t, 1, -1.0, fc->lo.h, fc->lo.u, fc->lo.v, &gh, &gu, &gv);
+        fc->hi.h = gh; fc->hi.u = gu; fc->hi.v = gv; fc->hi.z = zs;
+      }
+      dg2ref_hll(g, fc->lo.h, fc->lo.u, fc->lo.v, fc->hi.h, fc->hi.u, fc->hi.v, fc->flux);
+    }
+  for (int f = 0; f <= ny; ++f)
+    for (int i = 0; i < nx; ++i) {
+      face_t *fc = &c->yf[(size_t)f * nx + i];
+      size_t kl = (size_t)(f - 1) * nx + i, kr = (size_t)f * nx + i;
+      double zl = f > 0 ? c->z0[kl] : c->z0[kr];
+      double zr = f < ny ? c->z0[kr] : c->z0[kl];
+      double zs = zl > zr ? zl : zr;
+      if (f > 0) fc->lo = revise(h[kl], qx[kl], qy[kl], zl, zs, ht);
+      if (f < ny) fc->hi = revise(h[kr], qx[kr], qy[kr], zr, zs, ht);
+      double gh, gn, gt;
+      if (f == 0) {
+        ghost(c, &c->bs[i], t, 0, 1.0, fc->hi.h, fc->hi.v, fc->hi.u, &gh, &gn, &gt);
+        fc->lo.h = gh; fc->lo.v = gn; fc->lo.u = gt; fc->lo.z = zs;
+      } else if (f == ny) {
+        ghost(c, &c->bn[i], t, 0, -1.0, fc->lo.h, fc->lo.v, fc->lo.u, &gh, &gn, &gt);
+        fc->hi.h = gh; fc->hi.v = gn; fc->hi.u = gt; fc->hi.z = zs;
+      }
+      double o[3];
+      dg2ref_hll(g, fc->lo.h, fc->lo.v, fc->lo.u, fc->hi.h, fc->hi.v, fc->hi.u, o);
+      fc->flux[0] = o[0];
+      fc->flux[1] = o[2];
+      fc->flux[2] = o[1];
+    }
+  double rin = 0.0, rout = 0.0;
+  const double dx = c->cfg.dx;
+  for (int j = 0; j < ny; ++j) {
+    double fw = c->xf[(size_t)j * (nx + 1) + 0].flux[0] * dx;
+    double fe = -c->xf[(size_t)j * (nx + 1) + nx].flux[0] * dx;
+    if (fw > 0) rin += fw; else rout -= fw;
+    if (fe > 0) rin += fe; else rout -= fe;
+  }
+  for (int i = 0; i < nx; ++i) {
+    double fs = c->yf[(size_t)0 * nx + i].flux[0] * dx;
+    double fn = -c->yf[(size_t)ny * nx + i].flux[0] * dx;
+    if (fs > 0) rin += fs; else rout -= fs;
+    if (fn > 0) rin += fn; else rout -= fn;
+  }
+  *in_rate = rin;
+  *out_rate = rout;
+}
+
+static int do_step_fv1(dg2ref_ctx *c, double dt_max, double t_end, double *dt_used) {
+  const size_t n = c->n;
+  const int nx = c->nx, ny = c->ny;
+  const double g = c->cfg.g, ht = c->cfg.h_tol, dx = c->cfg.dx;
+  double dt = c->dt_next;
+  if (dt_max > 0.0 && dt_max < dt) dt = dt_max;
+  double t_next = c->t + dt;
+  if (t_end - c->t <= dt) {
+    dt = t_end - c->t;
+    t_next = t_end;
+  }
+  if (!(dt > 0.0)) return fail(c, DG2REF_E_NUMERIC, "non-positive time step %g at t=%g", dt, c->t);
+  /* friction at the centre: F = U with q replaced by the friction update */
+  memcpy(c->F, c->U, 9 * n * sizeof(double));
+  for (size_t k = 0; k < n; ++k) {
+    double q[2];
+    dg2ref_friction_point(g, c->manning[k], ht, dt, c->U[PL(0, 0) * n + k],
+                          c->U[PL(1, 0) * n + k], c->U[PL(2, 0) * n + k], q);
+    c->F[PL(1, 0) * n + k] = q[0];
+    c->F[PL(2, 0) * n + k] = q[1];
+  }
+  double in, out;
+  fv1_faces(c, c->F, c->t, &in, &out);
+  /* eq 7 with L0: flux differences and the bed source of each direction */
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      size_t k = (size_t)j * nx + i;
+      const face_t *fw = &c->xf[(size_t)j * (nx + 1) + i], *fe = &c->xf[(size_t)j * (nx + 1) + i + 1];
+      const face_t *fs = &c->yf[(size_t)j * nx + i], *fn = &c->yf[(size_t)(j + 1) * nx + i];
+      const side_t *W = &fw->hi, *E = &fe->lo, *Sd = &fs->hi, *N = &fn->lo;
+      double l0 = -(fe->flux[0] - fw->flux[0]) / dx - (fn->flux[0] - fs->flux[0]) / dx;
+      double l1 = -(fe->flux[1] - fw->flux[1]) / dx - (fn->flux[1] - fs->flux[1]) / dx -
+                  g * 0.5 * (E->h + W->h) * (E->z - W->z) / dx;
+      double l2 = -(fe->flux[2] - fw->flux[2]) / dx - (fn->flux[2] - fs->flux[2]) / dx -
+                  g * 0.5 * (N->h + Sd->h) * (N->z - Sd->z) / dx;
+      c->U[PL(0, 0) * n + k] = c->F[PL(0, 0) * n + k] + dt * l0;
+      c->U[PL(1, 0) * n + k] = c->F[PL(1, 0) * n + k] + dt * l1;
+      c->U[PL(2, 0) * n + k] = c->F[PL(2, 0) * n + k] + dt * l2;
+    }
+  int bad = 0;
+  double clip = pass_cleanup(c, c->U, &bad);
+  c->mass_in += dt * in;
+  c->mass_out += dt * out;
+  c->mass_clip += clip;
+  c->t = t_next;
+  c->step += 1;
+  c->dt_next = cfl_dt(c, c->U, c->t);
+  if (dt_used) *dt_used = dt;
+  if (bad) return fail(c, DG2REF_E_NUMERIC, "NaN in state at step %lld", (long long)c->step);
+  return DG2REF_OK;
+}
+
+static int any_step(dg2ref_ctx *c, double dt_max, double t_end, double *dt_used) {
+  return c->cfg.scheme == DG2REF_SCHEME_FV1 ? do_step_fv1(c, dt_max, t_end, dt_used)
+                                            : do_step(c, dt_max, t_end, dt_used);
+}
+
 int dg2ref_step(dg2ref_ctx *c, double dt_max, double *dt_used) {
   if (!c) return DG2REF_E_ARG;
-  return do_step(c, dt_max, INFINITY, dt_used);
+  return any_step(c, dt_max, INFINITY, dt_used);
 }
 
 int dg2ref_run(dg2ref_ctx *c, double t_end, int64_t *steps_taken) {
@@ -713,7 +846,7 @@ int dg2ref_run(dg2ref_ctx *c, double t_end, int64_t *steps_taken) {
   if (!(t_end >= c->t)) return fail(c, DG2REF_E_ARG, "t_end %g is before t %g", t_end, c->t);
   int64_t k = 0;
   while (c->t < t_end) {
-    int rc = do_step(c, 0.0, t_end, NULL);
+    int rc = any_step(c, 0.0, t_end, NULL);
     ++k;
     if (rc) {
       if (steps_taken) *steps_taken = k;
@@ -873,6 +1006,10 @@ int dg2ref_init(const dg2ref_config *cfg, const double *zv, const double *mannin
   } else {
     BAD("bad init mode %d", init_mode);
   }
+  if (cfg->scheme != DG2REF_SCHEME_DG2 && cfg->scheme != DG2REF_SCHEME_FV1) BAD("bad scheme");
+  if (cfg->scheme == DG2REF_SCHEME_FV1) /* piecewise constant: the means only (eq 5) */
+    for (int var = 0; var < 3; ++var)
+      for (int d = 1; d <= 2; ++d) memset(U + PL(var, d) * n, 0, n * sizeof(double));
   for (size_t k = 0; k < n; ++k) {
     if (U[PL(0, 0) * n + k] < 0.0) BAD("negative mean depth at cell %zu", k);
     if (U[PL(0, 0) * n + k] <= cfg->h_tol)

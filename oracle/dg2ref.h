@@ -28,6 +28,10 @@ extern "C" {
 
 enum { DG2REF_OK = 0, DG2REF_E_ARG = -1, DG2REF_E_NUMERIC = -3, DG2REF_E_STATE = -4 };
 
+/* schemes: DG2 (Sect. 2.1.1) or FV1 (Sect. 2.1.2: piecewise-constant h, qx, qy and
+ * bed, one forward-Euler step of L0 per time step) */
+enum { DG2REF_SCHEME_DG2 = 0, DG2REF_SCHEME_FV1 = 1 };
+
 /* boundary kinds */
 enum { DG2REF_BC_TRANSMISSIVE = 0, DG2REF_BC_WALL = 1, DG2REF_BC_FIXED = 2, DG2REF_BC_INFLOW = 3 };
 /* edges */
@@ -43,6 +47,8 @@ typedef struct {
   double t0;       /* initial time (s) */
   int32_t limiter; /* 1 = minmod on eta, qx, qy; 0 = off */
   int32_t edge_kind[4]; /* default kind per edge W, E, S, N (transmissive or wall) */
+  int32_t scheme;  /* DG2REF_SCHEME_*; FV1 keeps every slope plane zero and ignores the
+                      limiter; its Courant number is 0.5 */
 } dg2ref_config;
 
 typedef struct {
@@ -64,7 +70,8 @@ int dg2ref_init(const dg2ref_config *cfg, const double *zv, const double *mannin
                 double manning_scalar, int32_t init_mode, const double *init_data,
                 double eta_level, const dg2ref_boundary *bcs, int32_t n_bcs,
                 dg2ref_ctx **out);
-/* one RK2 step; dt = min(CFL dt, dt_max if > 0) */
+/* one time step (DG2: two RK2 stages; FV1: one forward-Euler step);
+ * dt = min(CFL dt, dt_max if > 0) */
 int dg2ref_step(dg2ref_ctx *c, double dt_max, double *dt_used);
 /* steps until t == t_end exactly */
 int dg2ref_run(dg2ref_ctx *c, double t_end, int64_t *steps_taken);

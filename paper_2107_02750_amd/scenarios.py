@@ -26,6 +26,9 @@ W, E, S, N = 0, 1, 2, 3
 # initial-condition modes
 MODE_PLANES, MODE_MEANS, MODE_VERTEX, MODE_LEVEL = 0, 1, 2, 3
 
+# schemes: DG2 (piecewise planar, RK2) and FV1 (piecewise constant, forward Euler)
+SCHEME_DG2, SCHEME_FV1 = 0, 1
+
 G_STD = 9.80665
 
 
@@ -64,6 +67,7 @@ class Scenario:
     t0: float = 0.0
     limiter: int = 1
     t_end: float = 0.0
+    scheme: int = SCHEME_DG2
 
     @property
     def cells(self) -> int:
@@ -71,6 +75,11 @@ class Scenario:
 
     def replace(self, **kw) -> "Scenario":
         return dataclasses.replace(self, **kw)
+
+    def as_fv1(self) -> "Scenario":
+        """The same inputs for the FV1 scheme, with its Courant number of 0.5."""
+        return dataclasses.replace(self, scheme=SCHEME_FV1, cfl=0.5,
+                                   name=self.name + "_fv1")
 
 
 def _flat_bed(nx: int, ny: int, z: float = 0.0) -> np.ndarray:
