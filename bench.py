@@ -100,6 +100,27 @@ def cpu_baseline(sc, budget_s):
                        f"workload ({secs:.1f} s)")
 
 
+def fv1_leg(dg2, S, n, steps, warmup):
+    """The FV1 scheme (one launch per step) on the same all-wet terrain, FP64 and FP32:
+    cell-updates/s and the fraction of the HBM roofline. Algorithmic bytes per cell and
+    step: the three means and one bed vertex read, the three means written."""
+    import torch
+    sc = S.fbm_channel_wet(n=n).as_fv1()
+    out = {"workload": f"FV1 (Courant number 0.5) on fbm+channel terrain {n}x{n}, every cell wet"}
+    for prec, tag, rb in ((dg2.FP64, "fp64", 8), (dg2.FP32, "fp32", 4)):
+        sim = dg2.DG2(sc, prec)
+        for _ in range(warmup):
+            sim.step(sync=False)
+        torch.cuda.synchronize()
+        el, tm = timed_steps(sim, steps)
+        ms = tm["ms_stage1"]
+        bytes_ = 7 * rb * n * n
+        out[tag] = {"value": n * n * steps / el, "unit": "cell-updates/s", "ms_per_launch": ms,
+                    "algorithmic_bytes_per_launch": bytes_,
+                    "roofline_frac": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
 def precision_form(dg2, S, n, t_end):
     """FP32 with per-tile bed datums against FP64.
 
@@ -305,6 +326,10 @@ def main():
                                 "spin_up_steps": spin, "spin_up_s": spin_s}
         print(f"[bench] as configured {out['as_configured']['value']:.4g} cell-updates/s, "
               f"wet {wet:.4f}", file=sys.stderr, flush=True)
+        out["fv1"] = fv1_leg(dg2, S, args.n, args.steps, args.warmup)
+        print(f"[bench] FV1 FP64 {out['fv1']['fp64']['value']:.4g} cell-updates/s "
+              f"({out['fv1']['fp64']['roofline_frac']:.2f} of HBM roofline), FP32 "
+              f"{out['fv1']['fp32']['value']:.4g}", file=sys.stderr, flush=True)
         out["precision_form"] = precision_form(dg2, S, args.n_urban, args.t_urban)
         pf = out["precision_form"]
         e = pf["fp32_datum"]["depth_error_vs_fp64"]

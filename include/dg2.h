@@ -81,6 +81,9 @@ enum {
                           h0 > 0, dry elsewhere; init_data unused */
 };
 
+/* schemes */
+enum { DG2_SCHEME_DG2 = 0, DG2_SCHEME_FV1 = 1 };
+
 /* limits of the boundary table */
 #define DG2_MAX_SEGMENTS 64
 #define DG2_MAX_KNOTS 8192 /* total over all inflow segments */
@@ -101,6 +104,11 @@ typedef struct {
                               dg2_bed_info */
   int32_t tile_x, tile_y;  /* tile of the stage kernels in cells: 0, 0 for the
                               precision's default, else one of dg2_tile_shapes */
+  int32_t scheme;          /* DG2_SCHEME_DG2, or DG2_SCHEME_FV1 (Sect. 2.1.2, eq 5-7):
+                              piecewise-constant h, qx, qy and bed (the means; every
+                              slope plane stays zero), L0 only, one forward-Euler step
+                              per time step, Courant number cfl (the paper uses 0.5);
+                              the limiter is not used */
 } dg2_config;
 
 typedef struct {
@@ -218,13 +226,13 @@ int dg2_tile_grid(const dg2_config *cfg, int32_t *tile_x, int32_t *tile_y, int32
  * ledger and health word. For each member a batch step is bitwise the same as a
  * dg2_step of that member alone (no dt_max). Steps are issued by replaying a HIP graph
  * of graph_steps steps (an even number, 2..256) captured on the members' stream.
- *  - members: n (1..DG2_MAX_BATCH) distinct contexts of one precision and tile shape,
- *    all created on the same stream. The batch borrows them: they must outlive it, and while it
+ *  - members: n (1..DG2_MAX_BATCH) distinct DG2-scheme contexts of one precision and
+ *    tile shape, all created on the same stream. The batch borrows them: they must outlive it, and while it
  *    exists they may be read and queried but not stepped, run or restored alone.
  *  - The batch allocates its launch table and status buffers (a few hundred KB of
  *    device memory and a little pinned host memory); dg2_batch_destroy frees them.
  *  - Errors: DG2_E_ARG (bad list, mixed precision, tile shape or streams, a repeated
- *    member),
+ *    member, an FV1 member),
  *    DG2_E_DEVICE, DG2_E_NUMERIC (a member's health word tripped; the message names
  *    it). */
 #define DG2_MAX_BATCH 256

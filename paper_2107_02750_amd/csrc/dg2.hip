@@ -108,6 +108,7 @@ struct dg2_ctx {
   char* ws;
   size_t n;
   bool fp32;
+  bool fv1;            // FV1 scheme: one launch per step, mean planes only
   bool datum;          // FP32 bed stored relative to per-tile datums
   double bed_q;        // quantum of the stored bed (0: unrounded)
   double bed_max;      // largest |z - datum| a tile reads (absolute |z| without datums)
@@ -191,6 +192,7 @@ Params<R> params(const dg2_ctx* c) {
   p.max_knots = DG2_MAX_KNOTS;
   p.limiter = c->cfg.limiter;
   p.parity = c->parity;
+  p.fv1 = c->fv1 ? 1 : 0;
   p.dx = R(c->cfg.dx);
   p.g = R(c->cfg.g);
   p.h_tol = R(c->cfg.h_tol);
@@ -207,13 +209,14 @@ Params<R> params(const dg2_ctx* c) {
 
 template <typename R, typename S>
 struct SmemBytes {
-  static int run() { return (int)sizeof(dg2k::Smem<R, S>); }
+  static int run(bool fv1) { return fv1 ? (int)sizeof(dg2k::SmemFV1<R, S>) : (int)sizeof(dg2k::Smem<R, S>); }
 };
 
 template <typename R, typename S>
 struct LaunchStep {
   static int run(dg2_ctx* c, double dt_max, double t_end) {
   Params<R> p = params<R>(c);
+  if (c->fv1) return run_fv1(c, p, dt_max, t_end);
   p.dt_max = dt_max;
   p.t_end = t_end;
   const dim3 grid(c->L.grid), block(c->L.threads);
@@ -237,6 +240,31 @@ struct LaunchStep {
   c->parity ^= 1;
   return DG2_OK;
   }
+
+  static int run_fv1(dg2_ctx* c, Params<R> p, double dt_max, double t_end) {
+    p.dt_max = dt_max;
+    p.t_end = t_end;
+    const dim3 grid(c->L.grid), block(c->L.threads);
+    hipEvent_t* e = nullptr;
+    if (c->timing) {
+      if (c->ev_used + 3 > c->ev.size()) {
+        const size_t old = c->ev.size();
+        c->ev.resize(old + 3 * 1024);
+        for (size_t k = old; k < c->ev.size(); ++k) HIPC(c, hipEventCreate(&c->ev[k]));
+      }
+      e = &c->ev[c->ev_used];
+      c->ev_used += 3;
+      HIPC(c, hipEventRecord(e[0], c->stream));
+    }
+    hipLaunchKernelGGL((dg2k::fv1_kernel<R, S>), grid, block, 0, c->stream, p);
+    HIPC(c, hipGetLastError());
+    if (e) {
+      HIPC(c, hipEventRecord(e[1], c->stream));
+      HIPC(c, hipEventRecord(e[2], c->stream));
+    }
+    c->parity ^= 1;
+    return DG2_OK;
+  }
 };
 
 template <typename R>
@@ -255,6 +283,12 @@ int pull_ctrl(dg2_ctx* c) {
   return DG2_OK;
 }
 
+// the CFL candidate of the current state, as pulled into h_ctrl
+unsigned long long dtc_bits(const dg2_ctx* c) {
+  const Ctrl& h = *c->h_ctrl;
+  return c->fv1 ? h.dtr[h.step[c->parity] % 3] : h.dtc[c->parity];
+}
+
 int check_health(dg2_ctx* c) {
   const int h = c->h_ctrl->health;
   if (h & 1) return fail(c, DG2_E_NUMERIC, "NaN in the state by step %lld", (long long)c->h_ctrl->step[c->parity]);
@@ -268,8 +302,10 @@ int launch_dtc(dg2_ctx* c, double t) {
   const R* u = reinterpret_cast<const R*>(c->ws + (c->parity ? c->L.u1 : c->L.u0));
   long long blocks = ((long long)c->n + 255) / 256;
   if (blocks > 2048) blocks = 2048;
+  Ctrl* ctl = reinterpret_cast<Ctrl*>(c->ws + c->L.ctrl);
+  unsigned long long* slot = c->fv1 ? &ctl->dtr[0] : &ctl->dtc[c->parity];  // step 0
   hipLaunchKernelGGL((dg2k::dtc_kernel<R>), dim3((unsigned)blocks), dim3(256), 0, c->stream, p, u, t,
-                     c->parity);
+                     slot);
   HIPC(c, hipGetLastError());
   return DG2_OK;
 }
@@ -289,6 +325,7 @@ int check_config(const dg2_config* cfg) {
   if (cfg->precision != DG2_FP64 && cfg->precision != DG2_FP32) return DG2_E_ARG;
   if (cfg->bed_datum != 0 && cfg->bed_datum != 1) return DG2_E_ARG;
   if (shape_index(*cfg) < 0) return DG2_E_UNSUPPORTED;
+  if (cfg->scheme != DG2_SCHEME_DG2 && cfg->scheme != DG2_SCHEME_FV1) return DG2_E_ARG;
   return DG2_OK;
 }
 
@@ -543,7 +580,7 @@ int dg2_batch_create(dg2_ctx* const* members, int32_t n, int32_t graph_steps, dg
   }
   for (int k = 0; k < n; ++k) {
     const dg2_ctx* c = members[k];
-    if (!c || c->in_batch || c->fp32 != members[0]->fp32 || c->stream != members[0]->stream ||
+    if (!c || c->in_batch || c->fv1 || c->fp32 != members[0]->fp32 || c->stream != members[0]->stream ||
         c->L.shape != members[0]->L.shape) {
       g_init_err = "members must be distinct free contexts of one precision and tile shape on one stream";
       return DG2_E_ARG;
@@ -767,6 +804,7 @@ int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, dou
   x->ws = reinterpret_cast<char*>(d_workspace);
   x->n = n;
   x->fp32 = c.precision == DG2_FP32;
+  x->fv1 = c.scheme == DG2_SCHEME_FV1;
   x->datum = x->fp32 && c.bed_datum == 1;
   x->has_manning = manning != nullptr;
   x->manning_scalar = manning_scalar;
@@ -788,8 +826,10 @@ int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, dou
     Ctrl ctrl{};
     ctrl.t[0] = ctrl.t[1] = c.t0;
     ctrl.dtc[0] = ctrl.dtc[1] = dg2k::INF_BITS;
+    ctrl.dtr[0] = ctrl.dtr[1] = ctrl.dtr[2] = dg2k::INF_BITS;
     err = dev(hipMemcpyAsync(x->ws + L.ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice, x->stream), "control block") ||
           dev(hipMemsetAsync(x->ws + L.ledger, 0, (size_t)L.n_tiles * 4 * sizeof(double), x->stream), "ledger") ||
+          dev(hipMemsetAsync(x->ws + L.u1, 0, 9 * n * (x->fp32 ? 4 : 8), x->stream), "state buffer") ||
           dev(hipMemcpyAsync(x->ws + L.bface, bface.data(), bface.size() * sizeof(int), hipMemcpyHostToDevice, x->stream), "boundary faces") ||
           dev(hipMemcpyAsync(x->ws + L.segs, segs.data(), segs.size() * sizeof(Seg), hipMemcpyHostToDevice, x->stream), "segments") ||
           dev(hipMemcpyAsync(x->ws + L.knots, knots.data(), knots.size() * sizeof(double), hipMemcpyHostToDevice, x->stream), "knots") ||
@@ -843,7 +883,7 @@ int dg2_run(dg2_ctx* c, double t_end, int64_t* steps_taken) {
     if (t >= t_end) return DG2_OK;
     // size the next batch from the current time step; steps issued past t_end are
     // no-ops that only carry the state over
-    const double m = __builtin_bit_cast(double, h.dtc[c->parity]);
+    const double m = __builtin_bit_cast(double, dtc_bits(c));
     double dt = std::isinf(m) ? c->cfg.dt_dry : c->cfg.cfl * m;
     double est = (t_end - t) / dt;
     batch = est < 1 ? 1 : (long long)std::ceil(est);
@@ -910,7 +950,7 @@ int dg2_next_dt(dg2_ctx* c, double* dt) {
   if (!c || !dt) return DG2_E_ARG;
   const int rc = pull_ctrl(c);
   if (rc) return rc;
-  const double m = __builtin_bit_cast(double, c->h_ctrl->dtc[c->parity]);
+  const double m = __builtin_bit_cast(double, dtc_bits(c));
   *dt = std::isinf(m) ? c->cfg.dt_dry : c->cfg.cfl * m;
   return DG2_OK;
 }
@@ -939,7 +979,8 @@ int dg2_get_state(dg2_ctx* c, void* host_dst) {
   double* s = reinterpret_cast<double*>(b + sizeof hdr);
   s[0] = c->h_ctrl->t[c->parity];
   s[1] = (double)c->h_ctrl->step[c->parity];
-  std::memcpy(&s[2], &c->h_ctrl->dtc[c->parity], 8);
+  const unsigned long long bits = dtc_bits(c);
+  std::memcpy(&s[2], &bits, 8);
   char* led = b + sizeof hdr + 24;
   HIPC(c, hipMemcpyAsync(led, c->ws + c->L.ledger, (size_t)c->L.n_tiles * 32, hipMemcpyDeviceToHost, c->stream));
   char* pl = led + (size_t)c->L.n_tiles * 32;
@@ -965,6 +1006,8 @@ int dg2_set_state(dg2_ctx* c, const void* host_src) {
   ctrl.t[c->parity] = s[0];
   ctrl.step[c->parity] = (long long)s[1];
   std::memcpy(&ctrl.dtc[c->parity], &s[2], 8);
+  for (int r = 0; r < 3; ++r) ctrl.dtr[r] = dg2k::INF_BITS;
+  std::memcpy(&ctrl.dtr[ctrl.step[c->parity] % 3], &s[2], 8);
   ctrl.health = 0;
   HIPC(c, hipMemcpyAsync(c->ws + c->L.ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice, c->stream));
   const char* led = b + sizeof hdr + 24;
@@ -1022,8 +1065,8 @@ int dg2_kernel_info(const dg2_ctx* c, int32_t* tile_x, int32_t* tile_y, int32_t*
   if (tile_y) *tile_y = c->L.ty;
   if (threads) *threads = c->L.threads;
   if (blocks) *blocks = c->L.grid;
-  if (lds_bytes) *lds_bytes = c->fp32 ? with_shape<float, SmemBytes>(c->L.shape)
-                                      : with_shape<double, SmemBytes>(c->L.shape);
+  if (lds_bytes) *lds_bytes = c->fp32 ? with_shape<float, SmemBytes>(c->L.shape, c->fv1)
+                                      : with_shape<double, SmemBytes>(c->L.shape, c->fv1);
   return DG2_OK;
 }
 

@@ -60,6 +60,10 @@ struct Ctrl {
   long long step[2];
   int health;                 // bit 0: NaN seen, bit 1: time step below 1e-12 s
   int pad;
+  // FV1 (one launch per step): the CFL candidate of step k lives in dtr[k % 3]; step k
+  // reads dtr[k % 3], reduces into dtr[(k + 1) % 3] and clears dtr[(k + 2) % 3], which
+  // no block of step k touches and step k - 1 has finished reading
+  unsigned long long dtr[3];
 };
 
 template <typename R>
@@ -76,7 +80,7 @@ struct Params {
   Ctrl* ctrl;
   double* ledger;              // per tile: in, out, clip, unused
   long long n;                 // nx * ny
-  int nx, ny, tx, ty, tiles_x, n_tiles, per_xcd, nsegs, max_knots, limiter, parity;
+  int nx, ny, tx, ty, tiles_x, n_tiles, per_xcd, nsegs, max_knots, limiter, parity, fv1;
   R dx, g, h_tol, n_scalar;
   double dxd, gd, cfl, htd, dt_dry, dt_max, t_end;
 };
@@ -1053,6 +1057,295 @@ __global__ void batch_status_kernel(const BatchTable<R>* __restrict__ tab, int p
 }
 
 // ---------------------------------------------------------------------------------
+// FV1 (Sect. 2.1.2, eq 5-7): piecewise-constant h, qx, qy and bed (z0 of eq 8), one
+// launch per time step: friction at the centre, HLL fluxes of the two cells' means
+// at each face after the temporary revision, L0 with the bed source
+// -g (hE* + hW*)/2 (zE** - zW**)/dx, and the forward-Euler update of eq 7. Only the
+// mean planes (0, 3, 6) are read and written; the slope planes stay zero.
+// ---------------------------------------------------------------------------------
+template <typename R, typename S>
+struct SmemFV1 {
+  static constexpr int TX = S::X, TY = S::Y, NT = TX * TY;
+  static constexpr int RX = TX + 2, RB = RX * (TY + 2);   // 1-cell halo
+  static constexpr int VX = TX + 3, VB = VX * (TY + 3);
+  R h[RB], qx[RB], qy[RB], z0[RB];  // box means after friction; bed means
+  R zv[VB];
+  R fx[3][RB];                      // flux through the west face of each position
+  R fy[3][RB];                      // flux through the south face of each position
+  double red[NT / 64][4];
+};
+
+// revised depth and bed of one side of a face (FP64: eta form; FP32: bed differences)
+template <typename R>
+__device__ __forceinline__ void fv1_side(R h, R zb, R zs, R& hs, R& zss) {
+  if constexpr (sizeof(R) == 8) {
+    const R eta = h + zb;
+    hs = fmax0(eta - zs);
+    zss = fminr(eta, zs);
+  } else {
+    const R d = h + (zb - zs);
+    hs = fmax0(d);
+    zss = zs + fminr(d, R(0));
+  }
+}
+
+template <typename R, typename S>
+__global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
+  using SM = SmemFV1<R, S>;
+  constexpr int TX = SM::TX, TY = SM::TY, NT = SM::NT, RX = SM::RX, RB = SM::RB;
+  constexpr int VX = SM::VX, VB = SM::VB;
+  constexpr int NRING = 2 * (TX + TY);
+  static_assert(NT % 64 == 0 && NRING <= NT && TY <= 64 && 64 + TX <= NT,
+                "tile must give whole waves and room for the halo items");
+  __shared__ SM sm;
+  const int b = blockIdx.x;
+  const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
+  if (tile >= p.n_tiles) return;
+  const int tid = threadIdx.x;
+  const int nx = p.nx, ny = p.ny;
+  const long long n = p.n;
+  const int i0 = (tile % p.tiles_x) * TX, j0 = (tile / p.tiles_x) * TY;
+  const int ci = i0 + tid % TX, cj = j0 + tid / TX;
+  const bool active = ci < nx && cj < ny;
+  const unsigned ck = (unsigned)(cj * nx + ci);
+  const R* __restrict__ hin = p.uin;
+  const R* __restrict__ qxin = p.uin + 3 * n;
+  const R* __restrict__ qyin = p.uin + 6 * n;
+
+  // the step's time step from the ring slot of this step
+  Ctrl* ctl = p.ctrl;
+  const int a = p.parity, o = 1 - p.parity;
+  const long long k = ctl->step[a];
+  const double t = ctl->t[a];
+  const double mm = __longlong_as_double((long long)ctl->dtr[k % 3]);
+  double dt = (mm == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * mm;
+  const double dt_cfl = dt;
+  if (p.dt_max > 0.0 && p.dt_max < dt) dt = p.dt_max;
+  double t_next = t + dt;
+  if (p.t_end - t <= dt) {
+    dt = p.t_end - t;
+    t_next = p.t_end;
+  }
+  if (!(dt > 0.0)) {  // past t_end: carry the state over
+    if (active) {
+      (p.vbuf)[ck] = hin[ck];
+      (p.vbuf + 3 * n)[ck] = qxin[ck];
+      (p.vbuf + 6 * n)[ck] = qyin[ck];
+    }
+    if (tile == 0 && tid == 0) {
+      ctl->t[o] = t;
+      ctl->step[o] = k;
+      ctl->dt_used[a] = 0.0;
+    }
+    return;
+  }
+  if (tile == 0 && tid == 0) {
+    ctl->t[o] = t_next;
+    ctl->step[o] = k + 1;
+    ctl->dt_used[a] = dt;
+    ctl->dtr[(k + 2) % 3] = INF_BITS;
+    if (dt_cfl < 1e-12) atomicOr(&ctl->health, 2);
+  }
+  const R dtr = R(dt);
+  const R ht = p.h_tol, g = p.g;
+  const R dT = (sizeof(R) == 4 && p.datum) ? p.datum[tile] : R(0);
+
+  // ---- phase 1: bed vertices, then the box means with friction applied ----
+  for (int r = tid; r < VB; r += NT) {
+    int iv = i0 - 1 + r % VX, jv = j0 - 1 + r / VX;
+    iv = iv < 0 ? 0 : (iv > nx ? nx : iv);
+    jv = jv < 0 ? 0 : (jv > ny ? ny : jv);
+    R z = p.zv[(unsigned)(jv * (nx + 1) + iv)];
+    if (sizeof(R) == 4 && p.datum) {
+      const int oi = iv < nx ? iv : nx - 1, oj = jv < ny ? jv : ny - 1;
+      z += p.datum[(oj / TY) * p.tiles_x + oi / TX] - dT;
+    }
+    sm.zv[r] = z;
+  }
+  auto load = [&](int ab, int bb) {  // box position (ab, bb), clamped to the domain
+    int i = i0 - 1 + ab, j = j0 - 1 + bb;
+    i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+    j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
+    const unsigned kk = (unsigned)(j * nx + i);
+    const R h = hin[kk];
+    R qx = qxin[kk], qy = qyin[kk];
+    const R nm = p.manning ? p.manning[kk] : p.n_scalar;
+    if (nm > R(0)) {
+      R dqx, dqy;
+      friction_inc(p.g * nm * nm * dtr, ht, h, qx, qy, dqx, dqy);
+      qx += dqx;
+      qy += dqy;
+    }
+    const int r = bb * RX + ab;
+    sm.h[r] = h;
+    sm.qx[r] = qx;
+    sm.qy[r] = qy;
+  };
+  const int ca = tid % TX + 1, cb = tid / TX + 1, cpos = cb * RX + ca;
+  load(ca, cb);
+  if (tid < NRING) {
+    int ab, bb;
+    if (tid < TY) { ab = 0; bb = tid + 1; }
+    else if (tid < 2 * TY) { ab = TX + 1; bb = tid - TY + 1; }
+    else if (tid < 2 * TY + TX) { ab = tid - 2 * TY + 1; bb = 0; }
+    else { ab = tid - 2 * TY - TX + 1; bb = TY + 1; }
+    load(ab, bb);
+  }
+  __syncthreads();
+  for (int r = tid; r < RB; r += NT) {  // bed means (eq 8, diagonal pairs)
+    const int ab = r % RX, bb = r / RX;
+    int i = i0 - 1 + ab, j = j0 - 1 + bb;
+    i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+    j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
+    const int va = i - (i0 - 1), vb = j - (j0 - 1);  // vertex box position of vertex (i, j)
+    const R sw = sm.zv[vb * VX + va], se = sm.zv[vb * VX + va + 1];
+    const R nw = sm.zv[(vb + 1) * VX + va], ne = sm.zv[(vb + 1) * VX + va + 1];
+    sm.z0[r] = R(0.25) * ((ne + sw) + (nw + se));
+  }
+  __syncthreads();
+
+  // ---- phase 2: HLL at the west and south face of each position ----
+  double led_in = 0.0, led_out = 0.0, led_clip = 0.0;
+  const double wflux = dt * p.dxd;
+  auto vel = [&](int r, R& u, R& v) {
+    const R h = sm.h[r];
+    const R rr = frcp(fmaxr(h, Tiny<R>::v));
+    u = h > ht ? sm.qx[r] * rr : R(0);
+    v = h > ht ? sm.qy[r] * rr : R(0);
+  };
+  // x-face f (between cells f-1 and f) of row j; r is the box position of cell f
+  auto xface = [&](int f, int j, int r) {
+    if (j >= ny || f > nx) return;
+    const int rl = f > 0 ? r - 1 : r, rr_ = f < nx ? r : r - 1;
+    const R zl = sm.z0[rl], zr = sm.z0[rr_];
+    const R zs = fmaxr(zl, zr);
+    R hl, zll, hr, zrr, ul, vl, ur, vr;
+    fv1_side(sm.h[rl], zl, zs, hl, zll);
+    fv1_side(sm.h[rr_], zr, zs, hr, zrr);
+    vel(rl, ul, vl);
+    vel(rr_, ur, vr);
+    if (f == 0) ghost(p, p.bface[j], t, true, R(1), hr, ur, vr, hl, ul, vl);
+    else if (f == nx) ghost(p, p.bface[ny + j], t, true, R(-1), hl, ul, vl, hr, ur, vr);
+    R o3[3];
+    hll(g, hl, ul, vl, hr, ur, vr, o3);
+    sm.fx[0][r] = o3[0];
+    sm.fx[1][r] = o3[1];
+    sm.fx[2][r] = o3[2];
+    if (f == 0) {
+      const double m = double(o3[0]) * wflux;
+      if (m > 0) led_in += m; else led_out -= m;
+    } else if (f == nx) {
+      const double m = -double(o3[0]) * wflux;
+      if (m > 0) led_in += m; else led_out -= m;
+    }
+  };
+  auto yface = [&](int i, int f, int r) {
+    if (i >= nx || f > ny) return;
+    const int rl = f > 0 ? r - RX : r, rr_ = f < ny ? r : r - RX;
+    const R zl = sm.z0[rl], zr = sm.z0[rr_];
+    const R zs = fmaxr(zl, zr);
+    R hl, zll, hr, zrr, ul, vl, ur, vr;
+    fv1_side(sm.h[rl], zl, zs, hl, zll);
+    fv1_side(sm.h[rr_], zr, zs, hr, zrr);
+    vel(rl, ul, vl);
+    vel(rr_, ur, vr);
+    // normal frame: (h, v, u)
+    if (f == 0) ghost(p, p.bface[2 * ny + i], t, false, R(1), hr, vr, ur, hl, vl, ul);
+    else if (f == ny) ghost(p, p.bface[2 * ny + nx + i], t, false, R(-1), hl, vl, ul, hr, vr, ur);
+    R o3[3];
+    hll(g, hl, vl, ul, hr, vr, ur, o3);
+    sm.fy[0][r] = o3[0];
+    sm.fy[1][r] = o3[2];  // x-momentum is tangential on a y-face
+    sm.fy[2][r] = o3[1];
+    if (f == 0) {
+      const double m = double(o3[0]) * wflux;
+      if (m > 0) led_in += m; else led_out -= m;
+    } else if (f == ny) {
+      const double m = -double(o3[0]) * wflux;
+      if (m > 0) led_in += m; else led_out -= m;
+    }
+  };
+  if (active) {
+    xface(ci, cj, cpos);
+    yface(ci, cj, cpos);
+  }
+  if (tid < TY) {  // the tile's east faces: west faces of the east halo column
+    const int j = j0 + tid;
+    if (i0 + TX <= nx) xface(i0 + TX, j, (tid + 1) * RX + TX + 1);
+  } else if (tid >= 64 && tid < 64 + TX) {  // north faces: south faces of the north halo row
+    const int i = i0 + tid - 64;
+    if (j0 + TY <= ny) yface(i, j0 + TY, (TY + 1) * RX + tid - 64 + 1);
+  }
+  // a tile cut by the domain edge: its last column / row owns the boundary face
+  if (active && ci == nx - 1 && i0 + TX > nx) xface(nx, cj, cpos + 1);
+  if (active && cj == ny - 1 && j0 + TY > ny) yface(ci, ny, cpos + RX);
+  __syncthreads();
+
+  // ---- phase 3: L0, the forward-Euler update, reductions ----
+  double my_dtc = __longlong_as_double((long long)INF_BITS);
+  if (active) {
+    const R h = sm.h[cpos], z = sm.z0[cpos];
+    auto side = [&](int nb, bool inside, R& hs, R& zss) {
+      const R zs = inside ? fmaxr(z, sm.z0[nb]) : z;
+      fv1_side(h, z, zs, hs, zss);
+    };
+    R hE, zE, hW, zW, hN, zN, hS, zS;
+    side(cpos + 1, ci < nx - 1, hE, zE);
+    side(cpos - 1, ci > 0, hW, zW);
+    side(cpos + RX, cj < ny - 1, hN, zN);
+    side(cpos - RX, cj > 0, hS, zS);
+    const R idx = R(1) / p.dx;
+    const R L0 = -(sm.fx[0][cpos + 1] - sm.fx[0][cpos]) * idx - (sm.fy[0][cpos + RX] - sm.fy[0][cpos]) * idx;
+    const R L1 = -(sm.fx[1][cpos + 1] - sm.fx[1][cpos]) * idx - (sm.fy[1][cpos + RX] - sm.fy[1][cpos]) * idx -
+                 g * R(0.5) * (hE + hW) * (zE - zW) * idx;
+    const R L2 = -(sm.fx[2][cpos + 1] - sm.fx[2][cpos]) * idx - (sm.fy[2][cpos + RX] - sm.fy[2][cpos]) * idx -
+                 g * R(0.5) * (hN + hS) * (zN - zS) * idx;
+    R u0 = h + dtr * L0, u1 = sm.qx[cpos] + dtr * L1, u2 = sm.qy[cpos] + dtr * L2;
+    if (u0 < R(0)) {
+      led_clip += -double(u0) * p.dxd * p.dxd;
+      u0 = R(0);
+    }
+    if (!(u0 > ht)) u1 = u2 = R(0);
+    if ((u0 + u1 + u2) != (u0 + u1 + u2)) atomicOr(&ctl->health, 1);
+    p.vbuf[ck] = u0;
+    (p.vbuf + 3 * n)[ck] = u1;
+    (p.vbuf + 6 * n)[ck] = u2;
+    my_dtc = cell_dtc(p, u0, R(0), R(0), u1, u2);
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+  const double r_in = wave_sum(led_in), r_out = wave_sum(led_out), r_clip = wave_sum(led_clip);
+  const double r_dt = wave_min(my_dtc);
+  if (lane == 0) {
+    sm.red[wv][0] = r_in;
+    sm.red[wv][1] = r_out;
+    sm.red[wv][2] = r_clip;
+    sm.red[wv][3] = r_dt;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double ai = 0, ao = 0, ac = 0, m = __longlong_as_double((long long)INF_BITS);
+    for (int w = 0; w < NT / 64; ++w) {
+      ai += sm.red[w][0];
+      ao += sm.red[w][1];
+      ac += sm.red[w][2];
+      m = sm.red[w][3] < m ? sm.red[w][3] : m;
+    }
+    if (ai != 0.0 || ao != 0.0 || ac != 0.0) {
+      double* led = p.ledger + 4 * (long long)tile;
+      led[0] += ai;
+      led[1] += ao;
+      led[2] += ac;
+    }
+    if (tile == 0) {
+      const double fm = forcing_dtc(p, t_next);
+      m = fm < m ? fm : m;
+    }
+    if (m != __longlong_as_double((long long)INF_BITS))
+      atomicMin(&ctl->dtr[(k + 1) % 3], (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // set-up and diagnostics kernels
 // ---------------------------------------------------------------------------------
 template <typename R>
@@ -1097,6 +1390,8 @@ __global__ void init_kernel(Params<R> p, const double* __restrict__ src, int mod
       c[2] = -z1y;
     }
   }
+  if (p.fv1)  // piecewise constant (eq 5): the means only
+    c[1] = c[2] = c[4] = c[5] = c[7] = c[8] = R(0);
   if (!(c[0] > p.h_tol))
     for (int q = 3; q < 9; ++q) c[q] = R(0);
   for (int q = 0; q < 9; ++q) p.vbuf[q * n + k] = c[q];
@@ -1105,7 +1400,8 @@ __global__ void init_kernel(Params<R> p, const double* __restrict__ src, int mod
 // CFL candidate of a whole state (set-up and resume): grid-stride min, one atomic per
 // block, plus the forcing at time t from block 0
 template <typename R>
-__global__ void dtc_kernel(Params<R> p, const R* __restrict__ u, double t, int slot) {
+__global__ void dtc_kernel(Params<R> p, const R* __restrict__ u, double t,
+                           unsigned long long* __restrict__ slot) {
   double m = __longlong_as_double((long long)INF_BITS);
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < p.n;
        k += (long long)gridDim.x * blockDim.x) {
@@ -1124,7 +1420,7 @@ __global__ void dtc_kernel(Params<R> p, const R* __restrict__ u, double t, int s
       m = fm < m ? fm : m;
     }
     if (m != __longlong_as_double((long long)INF_BITS))
-      atomicMin(&p.ctrl->dtc[slot], (unsigned long long)__double_as_longlong(m));
+      atomicMin(slot, (unsigned long long)__double_as_longlong(m));
   }
 }
 

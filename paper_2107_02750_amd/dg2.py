@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdg2.so")
 
 FP64, FP32 = 0, 1
+SCHEME_DG2, SCHEME_FV1 = 0, 1
 OK, E_ARG, E_DEVICE, E_NUMERIC, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 MAX_SEGMENTS, MAX_KNOTS = 64, 8192
 SYMBOLS = ("dg2_workspace_size", "dg2_init", "dg2_step", "dg2_run", "dg2_read",
@@ -34,7 +35,7 @@ class Config(C.Structure):
                 ("cfl", C.c_double), ("h_tol", C.c_double), ("dt_dry", C.c_double),
                 ("t0", C.c_double), ("precision", C.c_int32), ("limiter", C.c_int32),
                 ("edge_kind", C.c_int32 * 4), ("bed_datum", C.c_int32), ("tile_x", C.c_int32),
-                ("tile_y", C.c_int32)]
+                ("tile_y", C.c_int32), ("scheme", C.c_int32)]
 
 
 class Boundary(C.Structure):
@@ -117,7 +118,7 @@ def make_config(sc, precision: int, bed_datum: bool | None = None, tile=None) ->
     return Config(int(sc.nx), int(sc.ny), float(sc.dx), float(sc.g), float(sc.cfl),
                   float(sc.h_tol), float(sc.dt_dry), float(sc.t0), int(precision),
                   int(sc.limiter), (C.c_int32 * 4)(*[int(k) for k in sc.edge_kind]),
-                  int(bool(bed_datum)), tx, ty)
+                  int(bool(bed_datum)), tx, ty, int(getattr(sc, "scheme", 0)))
 
 
 def tile_shapes(precision: int) -> list:
