@@ -233,6 +233,8 @@ def main():
     ap.add_argument("--batch-t-end", type=float, default=1800.0, help="simulated seconds per scenario")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the FP64 timed region (for profiler runs)")
+    ap.add_argument("--fv1-only", action="store_true",
+                    help="only the FV1 leg, as its own JSON line (for profiler runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -244,6 +246,17 @@ def main():
 
     import torch
     from paper_2107_02750_amd import dg2, scenarios as S
+
+    if args.fv1_only:
+        r = fv1_leg(dg2, S, args.n, args.steps, args.warmup)
+        if args.calibrate_copy_mib:
+            a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device="cuda")
+            torch.empty_like(a).copy_(a)
+            torch.cuda.synchronize()
+        print(json.dumps({"metric": "FV1 cell-updates/s (forward-Euler step, FP64)",
+                          "value": r["fp64"]["value"], "unit": "cell-updates/s", "fv1": r}),
+              flush=True)
+        return
 
     sc = S.fbm_channel_wet(n=args.n)
     n_cells = sc.nx * sc.ny

@@ -283,10 +283,18 @@ int pull_ctrl(dg2_ctx* c) {
   return DG2_OK;
 }
 
+void set_cands_inf(Ctrl& c) {
+  for (auto* cd : {&c.dtc[0], &c.dtc[1], &c.dtr[0], &c.dtr[1], &c.dtr[2]})
+    for (auto& v : cd->s) v = dg2k::INF_BITS;
+}
+
 // the CFL candidate of the current state, as pulled into h_ctrl
 unsigned long long dtc_bits(const dg2_ctx* c) {
   const Ctrl& h = *c->h_ctrl;
-  return c->fv1 ? h.dtr[h.step[c->parity] % 3] : h.dtc[c->parity];
+  const dg2k::Cand& cd = c->fv1 ? h.dtr[h.step[c->parity] % 3] : h.dtc[c->parity];
+  unsigned long long m = dg2k::INF_BITS;
+  for (int k = 0; k < dg2k::NSLOT; ++k) m = std::min(m, cd.s[k * dg2k::SLOT_STRIDE]);
+  return m;
 }
 
 int check_health(dg2_ctx* c) {
@@ -303,7 +311,7 @@ int launch_dtc(dg2_ctx* c, double t) {
   long long blocks = ((long long)c->n + 255) / 256;
   if (blocks > 2048) blocks = 2048;
   Ctrl* ctl = reinterpret_cast<Ctrl*>(c->ws + c->L.ctrl);
-  unsigned long long* slot = c->fv1 ? &ctl->dtr[0] : &ctl->dtc[c->parity];  // step 0
+  unsigned long long* slot = c->fv1 ? &ctl->dtr[0].s[0] : &ctl->dtc[c->parity].s[0];  // step 0
   hipLaunchKernelGGL((dg2k::dtc_kernel<R>), dim3((unsigned)blocks), dim3(256), 0, c->stream, p, u, t,
                      slot);
   HIPC(c, hipGetLastError());
@@ -825,8 +833,7 @@ int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, dou
   if (!err) {
     Ctrl ctrl{};
     ctrl.t[0] = ctrl.t[1] = c.t0;
-    ctrl.dtc[0] = ctrl.dtc[1] = dg2k::INF_BITS;
-    ctrl.dtr[0] = ctrl.dtr[1] = ctrl.dtr[2] = dg2k::INF_BITS;
+    set_cands_inf(ctrl);
     err = dev(hipMemcpyAsync(x->ws + L.ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice, x->stream), "control block") ||
           dev(hipMemsetAsync(x->ws + L.ledger, 0, (size_t)L.n_tiles * 4 * sizeof(double), x->stream), "ledger") ||
           dev(hipMemsetAsync(x->ws + L.u1, 0, 9 * n * (x->fp32 ? 4 : 8), x->stream), "state buffer") ||
@@ -1005,9 +1012,9 @@ int dg2_set_state(dg2_ctx* c, const void* host_src) {
   Ctrl ctrl = *c->h_ctrl;
   ctrl.t[c->parity] = s[0];
   ctrl.step[c->parity] = (long long)s[1];
-  std::memcpy(&ctrl.dtc[c->parity], &s[2], 8);
-  for (int r = 0; r < 3; ++r) ctrl.dtr[r] = dg2k::INF_BITS;
-  std::memcpy(&ctrl.dtr[ctrl.step[c->parity] % 3], &s[2], 8);
+  set_cands_inf(ctrl);
+  std::memcpy(&ctrl.dtc[c->parity].s[0], &s[2], 8);
+  std::memcpy(&ctrl.dtr[ctrl.step[c->parity] % 3].s[0], &s[2], 8);
   ctrl.health = 0;
   HIPC(c, hipMemcpyAsync(c->ws + c->L.ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice, c->stream));
   const char* led = b + sizeof hdr + 24;

@@ -53,18 +53,37 @@ struct Seg {
 
 // control block shared by the launches of a context; slot [p] belongs to the step that
 // starts from state buffer p
+// A CFL candidate (min over cells of dx / (|u| + c), as positive-double bits, which
+// order like the values) is kept as NSLOT partial minima, each on its own 128-byte
+// line: block b reduces into slot b % NSLOT, so the blocks of a launch do not all
+// queue on one address, and a reader takes the min of the slots.
+constexpr int NSLOT = 16, SLOT_STRIDE = 16;
+struct Cand {
+  unsigned long long s[NSLOT * SLOT_STRIDE];
+};
+
 struct Ctrl {
   double t[2];
   double dt_used[2];
-  unsigned long long dtc[2];  // min over cells of dx / (|u| + c), as positive-double bits
   long long step[2];
   int health;                 // bit 0: NaN seen, bit 1: time step below 1e-12 s
   int pad;
-  // FV1 (one launch per step): the CFL candidate of step k lives in dtr[k % 3]; step k
+  alignas(128) Cand dtc[2];   // DG2: the candidate of the state in buffer p
+  // FV1 (one launch per step): the candidate of step k lives in dtr[k % 3]; step k
   // reads dtr[k % 3], reduces into dtr[(k + 1) % 3] and clears dtr[(k + 2) % 3], which
   // no block of step k touches and step k - 1 has finished reading
-  unsigned long long dtr[3];
+  Cand dtr[3];
 };
+
+// the candidate's value: min over its slots (every lane of the wave must take part)
+__device__ __forceinline__ double cand_read(const Cand& c);
+// post a block's candidate / clear all slots (one thread)
+__device__ __forceinline__ void cand_post(Cand& c, int block, double m) {
+  atomicMin(&c.s[(block % NSLOT) * SLOT_STRIDE], (unsigned long long)__double_as_longlong(m));
+}
+__device__ __forceinline__ void cand_clear(Cand& c) {
+  for (int k = 0; k < NSLOT; ++k) c.s[k * SLOT_STRIDE] = INF_BITS;
+}
 
 template <typename R>
 struct Params {
@@ -196,7 +215,7 @@ template <typename R>
 __device__ __forceinline__ void step_time(const Params<R>& p, double& t, double& dt, double& t_next,
                                           double& dt_cfl) {
   t = p.ctrl->t[p.parity];
-  const double m = __longlong_as_double((long long)p.ctrl->dtc[p.parity]);
+  const double m = cand_read(p.ctrl->dtc[p.parity]);
   double d = (m == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * m;
   dt_cfl = d;
   if (p.dt_max > 0.0 && p.dt_max < d) d = p.dt_max;
@@ -418,6 +437,13 @@ __device__ __forceinline__ double wave_min(double x) {
     x = y < x ? y : x;
   }
   return x;
+}
+
+__device__ __forceinline__ double cand_read(const Cand& c) {
+  const int lane = threadIdx.x & 63;
+  const double v = lane < NSLOT ? __longlong_as_double((long long)c.s[lane * SLOT_STRIDE])
+                                : __longlong_as_double((long long)INF_BITS);
+  return wave_min(v);
 }
 
 // ---------------------------------------------------------------------------------
@@ -952,7 +978,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
         m = fm < m ? fm : m;
       }
       if (m != __longlong_as_double((long long)INF_BITS))
-        atomicMin(&p.ctrl->dtc[1 - p.parity], (unsigned long long)__double_as_longlong(m));
+        cand_post(p.ctrl->dtc[1 - p.parity], tile, m);
     }
   }
 }
@@ -982,7 +1008,7 @@ __device__ __forceinline__ void stage_tile(const Params<R> p, const int tile) {
         const int a = p.parity, o = 1 - p.parity;
         c->t[o] = c->t[a];
         c->step[o] = c->step[a];
-        c->dtc[o] = c->dtc[a];
+        for (int q = 0; q < NSLOT; ++q) c->dtc[o].s[q * SLOT_STRIDE] = c->dtc[a].s[q * SLOT_STRIDE];
         c->dt_used[a] = 0.0;
       }
     }
@@ -993,7 +1019,7 @@ __device__ __forceinline__ void stage_tile(const Params<R> p, const int tile) {
     const int a = p.parity, o = 1 - p.parity;
     c->t[o] = t_next;
     c->step[o] = c->step[a] + 1;
-    c->dtc[o] = INF_BITS;
+    cand_clear(c->dtc[o]);
     c->dt_used[a] = dt;
     if (dt_cfl < 1e-12) atomicOr(&c->health, 2);
   }
@@ -1066,12 +1092,10 @@ __global__ void batch_status_kernel(const BatchTable<R>* __restrict__ tab, int p
 template <typename R, typename S>
 struct SmemFV1 {
   static constexpr int TX = S::X, TY = S::Y, NT = TX * TY;
-  static constexpr int RX = TX + 2, RB = RX * (TY + 2);   // 1-cell halo
-  static constexpr int VX = TX + 3, VB = VX * (TY + 3);
+  static constexpr int RX = TX + 2, RB = RX * (TY + 2);   // 1-cell cross halo
   R h[RB], qx[RB], qy[RB], z0[RB];  // box means after friction; bed means
-  R zv[VB];
-  R fx[3][RB];                      // flux through the west face of each position
-  R fy[3][RB];                      // flux through the south face of each position
+  R f[3][RB];                       // fluxes of one direction: the west (then south)
+                                    // face of each position
   double red[NT / 64][4];
 };
 
@@ -1092,8 +1116,7 @@ __device__ __forceinline__ void fv1_side(R h, R zb, R zs, R& hs, R& zss) {
 template <typename R, typename S>
 __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
   using SM = SmemFV1<R, S>;
-  constexpr int TX = SM::TX, TY = SM::TY, NT = SM::NT, RX = SM::RX, RB = SM::RB;
-  constexpr int VX = SM::VX, VB = SM::VB;
+  constexpr int TX = SM::TX, TY = SM::TY, NT = SM::NT, RX = SM::RX;
   constexpr int NRING = 2 * (TX + TY);
   static_assert(NT % 64 == 0 && NRING <= NT && TY <= 64 && 64 + TX <= NT,
                 "tile must give whole waves and room for the halo items");
@@ -1117,7 +1140,7 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
   const int a = p.parity, o = 1 - p.parity;
   const long long k = ctl->step[a];
   const double t = ctl->t[a];
-  const double mm = __longlong_as_double((long long)ctl->dtr[k % 3]);
+  const double mm = cand_read(ctl->dtr[k % 3]);
   double dt = (mm == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * mm;
   const double dt_cfl = dt;
   if (p.dt_max > 0.0 && p.dt_max < dt) dt = p.dt_max;
@@ -1143,25 +1166,14 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
     ctl->t[o] = t_next;
     ctl->step[o] = k + 1;
     ctl->dt_used[a] = dt;
-    ctl->dtr[(k + 2) % 3] = INF_BITS;
+    cand_clear(ctl->dtr[(k + 2) % 3]);
     if (dt_cfl < 1e-12) atomicOr(&ctl->health, 2);
   }
   const R dtr = R(dt);
   const R ht = p.h_tol, g = p.g;
-  const R dT = (sizeof(R) == 4 && p.datum) ? p.datum[tile] : R(0);
+  const R dT = tile_datum(p, i0, j0);
 
-  // ---- phase 1: bed vertices, then the box means with friction applied ----
-  for (int r = tid; r < VB; r += NT) {
-    int iv = i0 - 1 + r % VX, jv = j0 - 1 + r / VX;
-    iv = iv < 0 ? 0 : (iv > nx ? nx : iv);
-    jv = jv < 0 ? 0 : (jv > ny ? ny : jv);
-    R z = p.zv[(unsigned)(jv * (nx + 1) + iv)];
-    if (sizeof(R) == 4 && p.datum) {
-      const int oi = iv < nx ? iv : nx - 1, oj = jv < ny ? jv : ny - 1;
-      z += p.datum[(oj / TY) * p.tiles_x + oi / TX] - dT;
-    }
-    sm.zv[r] = z;
-  }
+  // ---- phase 1: the box means (friction applied) and bed means of the box cells ----
   auto load = [&](int ab, int bb) {  // box position (ab, bb), clamped to the domain
     int i = i0 - 1 + ab, j = j0 - 1 + bb;
     i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
@@ -1176,10 +1188,13 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
       qx += dqx;
       qy += dqy;
     }
+    const R sw = zvat(p, i, j, dT), se = zvat(p, i + 1, j, dT);
+    const R nw = zvat(p, i, j + 1, dT), ne = zvat(p, i + 1, j + 1, dT);
     const int r = bb * RX + ab;
     sm.h[r] = h;
     sm.qx[r] = qx;
     sm.qy[r] = qy;
+    sm.z0[r] = R(0.25) * ((ne + sw) + (nw + se));  // eq 8, diagonal pairs
   };
   const int ca = tid % TX + 1, cb = tid / TX + 1, cpos = cb * RX + ca;
   load(ca, cb);
@@ -1192,19 +1207,7 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
     load(ab, bb);
   }
   __syncthreads();
-  for (int r = tid; r < RB; r += NT) {  // bed means (eq 8, diagonal pairs)
-    const int ab = r % RX, bb = r / RX;
-    int i = i0 - 1 + ab, j = j0 - 1 + bb;
-    i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
-    j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
-    const int va = i - (i0 - 1), vb = j - (j0 - 1);  // vertex box position of vertex (i, j)
-    const R sw = sm.zv[vb * VX + va], se = sm.zv[vb * VX + va + 1];
-    const R nw = sm.zv[(vb + 1) * VX + va], ne = sm.zv[(vb + 1) * VX + va + 1];
-    sm.z0[r] = R(0.25) * ((ne + sw) + (nw + se));
-  }
-  __syncthreads();
 
-  // ---- phase 2: HLL at the west and south face of each position ----
   double led_in = 0.0, led_out = 0.0, led_clip = 0.0;
   const double wflux = dt * p.dxd;
   auto vel = [&](int r, R& u, R& v) {
@@ -1213,10 +1216,14 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
     u = h > ht ? sm.qx[r] * rr : R(0);
     v = h > ht ? sm.qy[r] * rr : R(0);
   };
-  // x-face f (between cells f-1 and f) of row j; r is the box position of cell f
-  auto xface = [&](int f, int j, int r) {
-    if (j >= ny || f > nx) return;
-    const int rl = f > 0 ? r - 1 : r, rr_ = f < nx ? r : r - 1;
+  // HLL through face f of a line (x: f between cells f-1 and f of row `line`; y: f
+  // between rows f-1 and f of column `line`); r is the box position of cell f, st the
+  // box step across the face; the flux goes to sm.f at r, in (mass, x-mom, y-mom)
+  auto face = [&](bool xdir, int f, int line, int r) {
+    const int nf = xdir ? nx : ny;
+    if (line >= (xdir ? ny : nx) || f > nf) return;
+    const int st = xdir ? 1 : RX;
+    const int rl = f > 0 ? r - st : r, rr_ = f < nf ? r : r - st;
     const R zl = sm.z0[rl], zr = sm.z0[rr_];
     const R zs = fmaxr(zl, zr);
     R hl, zll, hr, zrr, ul, vl, ur, vr;
@@ -1224,82 +1231,65 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
     fv1_side(sm.h[rr_], zr, zs, hr, zrr);
     vel(rl, ul, vl);
     vel(rr_, ur, vr);
-    if (f == 0) ghost(p, p.bface[j], t, true, R(1), hr, ur, vr, hl, ul, vl);
-    else if (f == nx) ghost(p, p.bface[ny + j], t, true, R(-1), hl, ul, vl, hr, ur, vr);
+    // normal frame: x faces (h, u, v), y faces (h, v, u)
+    R nl = xdir ? ul : vl, tl = xdir ? vl : ul, nr = xdir ? ur : vr, tr = xdir ? vr : ur;
+    const int eo = xdir ? 0 : 2 * ny;
+    if (f == 0) ghost(p, p.bface[eo + line], t, xdir, R(1), hr, nr, tr, hl, nl, tl);
+    else if (f == nf) ghost(p, p.bface[eo + (xdir ? ny : nx) + line], t, xdir, R(-1), hl, nl, tl, hr, nr, tr);
     R o3[3];
-    hll(g, hl, ul, vl, hr, ur, vr, o3);
-    sm.fx[0][r] = o3[0];
-    sm.fx[1][r] = o3[1];
-    sm.fx[2][r] = o3[2];
+    hll(g, hl, nl, tl, hr, nr, tr, o3);
+    sm.f[0][r] = o3[0];
+    sm.f[1][r] = xdir ? o3[1] : o3[2];  // x-momentum is tangential on a y-face
+    sm.f[2][r] = xdir ? o3[2] : o3[1];
     if (f == 0) {
       const double m = double(o3[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
-    } else if (f == nx) {
+    } else if (f == nf) {
       const double m = -double(o3[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
     }
   };
-  auto yface = [&](int i, int f, int r) {
-    if (i >= nx || f > ny) return;
-    const int rl = f > 0 ? r - RX : r, rr_ = f < ny ? r : r - RX;
-    const R zl = sm.z0[rl], zr = sm.z0[rr_];
-    const R zs = fmaxr(zl, zr);
-    R hl, zll, hr, zrr, ul, vl, ur, vr;
-    fv1_side(sm.h[rl], zl, zs, hl, zll);
-    fv1_side(sm.h[rr_], zr, zs, hr, zrr);
-    vel(rl, ul, vl);
-    vel(rr_, ur, vr);
-    // normal frame: (h, v, u)
-    if (f == 0) ghost(p, p.bface[2 * ny + i], t, false, R(1), hr, vr, ur, hl, vl, ul);
-    else if (f == ny) ghost(p, p.bface[2 * ny + nx + i], t, false, R(-1), hl, vl, ul, hr, vr, ur);
-    R o3[3];
-    hll(g, hl, vl, ul, hr, vr, ur, o3);
-    sm.fy[0][r] = o3[0];
-    sm.fy[1][r] = o3[2];  // x-momentum is tangential on a y-face
-    sm.fy[2][r] = o3[1];
-    if (f == 0) {
-      const double m = double(o3[0]) * wflux;
-      if (m > 0) led_in += m; else led_out -= m;
-    } else if (f == ny) {
-      const double m = -double(o3[0]) * wflux;
-      if (m > 0) led_in += m; else led_out -= m;
-    }
+  // the cell's own state and its revised depth and bed at one face
+  const R h = sm.h[cpos], z = sm.z0[cpos];
+  auto side = [&](int nb, bool inside, R& hs, R& zss) {
+    const R zs = inside ? fmaxr(z, sm.z0[nb]) : z;
+    fv1_side(h, z, zs, hs, zss);
   };
-  if (active) {
-    xface(ci, cj, cpos);
-    yface(ci, cj, cpos);
-  }
-  if (tid < TY) {  // the tile's east faces: west faces of the east halo column
-    const int j = j0 + tid;
-    if (i0 + TX <= nx) xface(i0 + TX, j, (tid + 1) * RX + TX + 1);
-  } else if (tid >= 64 && tid < 64 + TX) {  // north faces: south faces of the north halo row
-    const int i = i0 + tid - 64;
-    if (j0 + TY <= ny) yface(i, j0 + TY, (TY + 1) * RX + tid - 64 + 1);
-  }
-  // a tile cut by the domain edge: its last column / row owns the boundary face
-  if (active && ci == nx - 1 && i0 + TX > nx) xface(nx, cj, cpos + 1);
-  if (active && cj == ny - 1 && j0 + TY > ny) yface(ci, ny, cpos + RX);
-  __syncthreads();
+  const R idx = R(1) / p.dx;
+  R L0 = R(0), L1 = R(0), L2 = R(0);
 
-  // ---- phase 3: L0, the forward-Euler update, reductions ----
-  double my_dtc = __longlong_as_double((long long)INF_BITS);
+  // ---- phase 2: x faces (each west face once; the tile's east faces by halo items) ----
+  if (active) face(true, ci, cj, cpos);
+  if (tid < TY) {
+    if (i0 + TX <= nx) face(true, i0 + TX, j0 + tid, (tid + 1) * RX + TX + 1);
+  }
+  if (active && ci == nx - 1 && i0 + TX > nx) face(true, nx, cj, cpos + 1);  // cut tile
+  __syncthreads();
   if (active) {
-    const R h = sm.h[cpos], z = sm.z0[cpos];
-    auto side = [&](int nb, bool inside, R& hs, R& zss) {
-      const R zs = inside ? fmaxr(z, sm.z0[nb]) : z;
-      fv1_side(h, z, zs, hs, zss);
-    };
-    R hE, zE, hW, zW, hN, zN, hS, zS;
+    R hE, zE, hW, zW;
     side(cpos + 1, ci < nx - 1, hE, zE);
     side(cpos - 1, ci > 0, hW, zW);
+    L0 = -(sm.f[0][cpos + 1] - sm.f[0][cpos]) * idx;
+    L1 = -(sm.f[1][cpos + 1] - sm.f[1][cpos]) * idx - g * R(0.5) * (hE + hW) * (zE - zW) * idx;
+    L2 = -(sm.f[2][cpos + 1] - sm.f[2][cpos]) * idx;
+  }
+  __syncthreads();
+
+  // ---- phase 3: y faces, then L0 and the forward-Euler update ----
+  if (active) face(false, cj, ci, cpos);
+  if (tid >= 64 && tid < 64 + TX) {
+    if (j0 + TY <= ny) face(false, j0 + TY, i0 + tid - 64, (TY + 1) * RX + tid - 64 + 1);
+  }
+  if (active && cj == ny - 1 && j0 + TY > ny) face(false, ny, ci, cpos + RX);  // cut tile
+  __syncthreads();
+  double my_dtc = __longlong_as_double((long long)INF_BITS);
+  if (active) {
+    R hN, zN, hS, zS;
     side(cpos + RX, cj < ny - 1, hN, zN);
     side(cpos - RX, cj > 0, hS, zS);
-    const R idx = R(1) / p.dx;
-    const R L0 = -(sm.fx[0][cpos + 1] - sm.fx[0][cpos]) * idx - (sm.fy[0][cpos + RX] - sm.fy[0][cpos]) * idx;
-    const R L1 = -(sm.fx[1][cpos + 1] - sm.fx[1][cpos]) * idx - (sm.fy[1][cpos + RX] - sm.fy[1][cpos]) * idx -
-                 g * R(0.5) * (hE + hW) * (zE - zW) * idx;
-    const R L2 = -(sm.fx[2][cpos + 1] - sm.fx[2][cpos]) * idx - (sm.fy[2][cpos + RX] - sm.fy[2][cpos]) * idx -
-                 g * R(0.5) * (hN + hS) * (zN - zS) * idx;
+    L0 += -(sm.f[0][cpos + RX] - sm.f[0][cpos]) * idx;
+    L1 += -(sm.f[1][cpos + RX] - sm.f[1][cpos]) * idx;
+    L2 += -(sm.f[2][cpos + RX] - sm.f[2][cpos]) * idx - g * R(0.5) * (hN + hS) * (zN - zS) * idx;
     R u0 = h + dtr * L0, u1 = sm.qx[cpos] + dtr * L1, u2 = sm.qy[cpos] + dtr * L2;
     if (u0 < R(0)) {
       led_clip += -double(u0) * p.dxd * p.dxd;
@@ -1313,14 +1303,20 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
     my_dtc = cell_dtc(p, u0, R(0), R(0), u1, u2);
   }
   const int lane = tid & 63, wv = tid >> 6;
-  const double r_in = wave_sum(led_in), r_out = wave_sum(led_out), r_clip = wave_sum(led_clip);
-  const double r_dt = wave_min(my_dtc);
-  if (lane == 0) {
-    sm.red[wv][0] = r_in;
-    sm.red[wv][1] = r_out;
-    sm.red[wv][2] = r_clip;
-    sm.red[wv][3] = r_dt;
+  // ledger terms exist only where a tile touches the domain edge or a depth was clipped
+  const bool edge_tile = i0 == 0 || j0 == 0 || i0 + TX >= nx || j0 + TY >= ny;
+  if (edge_tile || __any(led_clip != 0.0)) {
+    const double r_in = wave_sum(led_in), r_out = wave_sum(led_out), r_clip = wave_sum(led_clip);
+    if (lane == 0) {
+      sm.red[wv][0] = r_in;
+      sm.red[wv][1] = r_out;
+      sm.red[wv][2] = r_clip;
+    }
+  } else if (lane == 0) {
+    sm.red[wv][0] = sm.red[wv][1] = sm.red[wv][2] = 0.0;
   }
+  const double r_dt = wave_min(my_dtc);
+  if (lane == 0) sm.red[wv][3] = r_dt;
   __syncthreads();
   if (tid == 0) {
     double ai = 0, ao = 0, ac = 0, m = __longlong_as_double((long long)INF_BITS);
@@ -1341,7 +1337,7 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
       m = fm < m ? fm : m;
     }
     if (m != __longlong_as_double((long long)INF_BITS))
-      atomicMin(&ctl->dtr[(k + 1) % 3], (unsigned long long)__double_as_longlong(m));
+      cand_post(ctl->dtr[(k + 1) % 3], tile, m);
   }
 }
 
