@@ -253,6 +253,37 @@ def batch_scenarios(count: int = 64, seed: int = 400, side_lo: int = 256, side_h
     return out
 
 
+def adjoint_case(n: int = 512, dx: float = 5.0, seed: int = 5, zones: int = 4,
+                 n_knots: int = 48, t_span: float = 400.0, eta: float = 25.0,
+                 band: float = 60.0) -> Scenario:
+    """A fully wet, limiter-off flow for gradient studies: the fBm terrain (seed) under
+    still water at level eta plus a weak uniform eastward discharge, Manning n constant
+    on each of zones x zones rectangular blocks (n ~ U(0.02, 0.05)), and an inflow
+    hydrograph of n_knots knots spread over t_span (Q ~ U(20, 120) m^3/s) through the
+    west-edge faces of a central band; other edges transmissive."""
+    rng = np.random.default_rng(seed + 5000)
+    zv = fbm_vertices(n + 1, seed, 0.8, 20.0)
+    depth = eta - zv
+    vert = np.stack([depth, np.full_like(depth, 0.5), np.zeros_like(depth)])
+    n_zone = rng.uniform(0.02, 0.05, size=(zones, zones))
+    zi = np.minimum(np.arange(n) * zones // n, zones - 1)
+    manning = n_zone[zi[:, None], zi[None, :]]
+    rows = int(round(band / dx))
+    j0 = n // 2 - rows // 2
+    t_k = np.linspace(0.0, t_span, n_knots)
+    q_k = rng.uniform(20.0, 120.0, size=n_knots)
+    bc = Boundary(W, INFLOW, j0, j0 + rows, t_k, q_k)
+    return Scenario("adjoint_case", n, n, dx, zv, MODE_VERTEX, vert, manning=manning,
+                    boundaries=[bc], limiter=0, t_end=t_span)
+
+
+def zone_index(n: int, zones: int = 4) -> np.ndarray:
+    """Zone number (row-major over zones x zones blocks) of every cell of an n x n grid,
+    as used by adjoint_case."""
+    zi = np.minimum(np.arange(n) * zones // n, zones - 1)
+    return zi[:, None] * zones + zi[None, :]
+
+
 def urban_blocks(n: int = 2048, dx: float = 2.0, seed: int = 3, n_blocks: int = 4000,
                  side_min: float = 5.0, side_max: float = 30.0, height: float = 10.0,
                  h_in: float = 1.0, u_in: float = 2.0, manning: float = 0.02,
