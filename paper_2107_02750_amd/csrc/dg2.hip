@@ -13,6 +13,7 @@
 
 #include "dg2.h"
 #include "dg2_kernels.hpp"
+#include "dg2_adjoint.hpp"
 
 using dg2k::Ctrl;
 using dg2k::Params;
@@ -124,6 +125,8 @@ struct dg2_ctx {
   int64_t t_steps;
   double t_ms1, t_ms2;
   bool in_batch;       // borrowed by a batch: not stepped alone
+  double dt_fix;       // > 0: the next steps take exactly this dt (a tape's schedule)
+  std::vector<int> knot_count;  // hydrograph knots of each boundary segment
   std::string err;
 };
 
@@ -204,6 +207,7 @@ Params<R> params(const dg2_ctx* c) {
   p.dt_dry = c->cfg.dt_dry;
   p.dt_max = 0.0;
   p.t_end = INFINITY;
+  p.dt_fix = c->dt_fix;
   return p;
 }
 
@@ -823,6 +827,8 @@ int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, dou
   x->t_steps = 0;
   x->t_ms1 = x->t_ms2 = 0;
   x->in_batch = false;
+  x->dt_fix = 0.0;
+  for (int s = 0; s < n_bcs; ++s) x->knot_count.push_back(bcs[s].kind == DG2_BC_INFLOW ? bcs[s].n_knots : 0);
   auto dev = [&](hipError_t e, const char* what) {
     if (e == hipSuccess) return false;
     g_init_err = std::string(what) + ": " + hipGetErrorString(e);
@@ -1103,6 +1109,350 @@ int dg2_tile_grid(const dg2_config* cfg, int32_t* tile_x, int32_t* tile_y, int32
   if (tiles_x) *tiles_x = L.tiles_x;
   if (tiles_y) *tiles_y = L.tiles_y;
   return DG2_OK;
+}
+
+int dg2_set_manning(dg2_ctx* c, const double* manning) {
+  if (!c || !manning) return DG2_E_ARG;
+  if (!c->has_manning) return fail(c, DG2_E_STATE, "context has no per-cell Manning plane");
+  for (size_t k = 0; k < c->n; ++k)
+    if (!(manning[k] >= 0) || !std::isfinite(manning[k])) return fail(c, DG2_E_ARG, "bad Manning n at cell %zu", k);
+  double* st = nullptr;
+  HIPC(c, hipMalloc(&st, c->n * sizeof(double)));
+  hipError_t e = hipMemcpyAsync(st, manning, c->n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  const unsigned blocks = (unsigned)((c->n + 255) / 256);
+  if (e == hipSuccess) {
+    if (c->fp32)
+      hipLaunchKernelGGL((dg2k::convert_kernel<float>), dim3(blocks), dim3(256), 0, c->stream, st,
+                         reinterpret_cast<float*>(c->ws + c->L.man), (long long)c->n);
+    else
+      hipLaunchKernelGGL((dg2k::convert_kernel<double>), dim3(blocks), dim3(256), 0, c->stream, st,
+                         reinterpret_cast<double*>(c->ws + c->L.man), (long long)c->n);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(st);
+  if (e != hipSuccess) return fail(c, DG2_E_DEVICE, "set Manning: %s", hipGetErrorString(e));
+  return DG2_OK;
+}
+
+int dg2_set_hydrograph(dg2_ctx* c, int32_t seg, const double* q_knots) {
+  if (!c || !q_knots || seg < 0 || seg >= (int)c->knot_count.size()) return DG2_E_ARG;
+  const int nk = c->knot_count[seg];
+  if (nk <= 0) return fail(c, DG2_E_ARG, "segment %d has no hydrograph", seg);
+  int k0 = 0;
+  for (int s2 = 0; s2 < seg; ++s2) k0 += c->knot_count[s2];
+  for (int k = 0; k < nk; ++k)
+    if (!(q_knots[k] >= 0) || !std::isfinite(q_knots[k])) return fail(c, DG2_E_ARG, "bad knot %d", k);
+  double* kq = reinterpret_cast<double*>(c->ws + c->L.knots) + DG2_MAX_KNOTS + k0;
+  HIPC(c, hipMemcpyAsync(kq, q_knots, nk * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return DG2_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// tape: recorded forward run and its discrete adjoint
+// ---------------------------------------------------------------------------------
+struct dg2_tape {
+  dg2_ctx* c;
+  int n_steps, K, n_ckpt, ng;
+  std::vector<double> dts, t;  // t[k]: time at the start of step k
+  double* ckpt;                // n_ckpt states (9n each)
+  double* seg;                 // K states
+  double* V;                   // stage-1 V^n and U^int of the step being reversed
+  double* Ui;
+  double* lam;                 // cotangent of the current state
+  double* nu1;
+  double* nu2;
+  double* gman;                // dJ/dn per cell
+  double* gq;                  // dJ/dQ(t) per (step, stage, segment)
+  double* gh;                  // gauge depths (n_steps + 1) x ng
+  double* dj;                  // dJ/dh on the device
+  int* gidx;
+  int* regime;
+  dg2k::Ctrl* ctrl;            // the tape's own control block for recomputation
+  double* ledger;
+  double* d_t;                 // the step start times on the device
+  bool recorded;
+  std::string err;
+};
+
+namespace {
+
+int tfail(dg2_tape* tp, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  tp->err = buf;
+  return code;
+}
+
+#define THIPC(tp, call)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return tfail(tp, DG2_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename R, typename S>
+struct TapeStage {
+  static int run(dg2_tape* tp, Params<R> p, int stage) {
+    const dim3 grid(tp->c->L.grid), block(tp->c->L.threads);
+    if (stage == 1)
+      hipLaunchKernelGGL((dg2k::stage_kernel<R, S, 1>), grid, block, 0, tp->c->stream, p);
+    else
+      hipLaunchKernelGGL((dg2k::stage_kernel<R, S, 2>), grid, block, 0, tp->c->stream, p);
+    THIPC(tp, hipGetLastError());
+    return DG2_OK;
+  }
+};
+
+// parameters of a recomputed step k from state U into the tape's buffers
+Params<double> tape_params(dg2_tape* tp, const double* U, int k) {
+  dg2_ctx* c = tp->c;
+  Params<double> p = params<double>(c);
+  p.uin = U;
+  p.vbuf = tp->V;
+  p.ui = tp->Ui;
+  p.ctrl = tp->ctrl;
+  p.ledger = tp->ledger;
+  p.parity = 0;
+  p.dt_fix = tp->dts[k];
+  p.dt_max = 0.0;
+  p.t_end = INFINITY;
+  return p;
+}
+
+// set the tape's control block to time t[k] (stream ordered)
+int tape_set_time(dg2_tape* tp, int k) {
+  hipLaunchKernelGGL(dg2k::set_time_kernel, dim3(1), dim3(64), 0, tp->c->stream, tp->ctrl, tp->d_t, k);
+  THIPC(tp, hipGetLastError());
+  return DG2_OK;
+}
+
+// recompute step k from U: V^n -> tp->V, U^int -> tp->Ui; with both stages, U^{n+1} in tp->V
+int tape_step(dg2_tape* tp, const double* U, int k, bool both) {
+  int rc = tape_set_time(tp, k);
+  if (rc) return rc;
+  Params<double> p = tape_params(tp, U, k);
+  if ((rc = with_shape<double, TapeStage>(tp->c->L.shape, tp, p, 1))) return rc;
+  if (both) rc = with_shape<double, TapeStage>(tp->c->L.shape, tp, p, 2);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg2_tape_create(dg2_ctx* c, int32_t n_steps, const double* dts, const int32_t* gauges,
+                    int32_t n_gauges, int32_t checkpoint_every, dg2_tape** out) {
+  g_init_err.clear();
+  if (!out) return DG2_E_ARG;
+  *out = nullptr;
+  if (!c || n_steps < 1 || !dts || n_gauges < 0 || (n_gauges > 0 && !gauges) || checkpoint_every < 0) {
+    g_init_err = "bad tape arguments";
+    return DG2_E_ARG;
+  }
+  if (c->fp32 || c->fv1 || c->cfg.limiter != 0 || c->in_batch) {
+    g_init_err = "the adjoint covers FP64 DG2 contexts with the limiter off";
+    return DG2_E_UNSUPPORTED;
+  }
+  for (int k = 0; k < n_steps; ++k)
+    if (!(dts[k] > 0) || !std::isfinite(dts[k])) {
+      g_init_err = "time steps must be positive";
+      return DG2_E_ARG;
+    }
+  for (int g = 0; g < n_gauges; ++g)
+    if (gauges[g] < 0 || (size_t)gauges[g] >= c->n) {
+      g_init_err = "gauge outside the grid";
+      return DG2_E_ARG;
+    }
+  dg2_tape* tp = new (std::nothrow) dg2_tape();
+  if (!tp) return DG2_E_ARG;
+  tp->c = c;
+  tp->n_steps = n_steps;
+  tp->K = checkpoint_every > 0 ? checkpoint_every : (int)std::ceil(std::sqrt((double)n_steps));
+  tp->n_ckpt = (n_steps + tp->K - 1) / tp->K;
+  tp->ng = n_gauges;
+  tp->dts.assign(dts, dts + n_steps);
+  tp->recorded = false;
+  const size_t st = 9 * c->n * sizeof(double);
+  int nseg = (int)c->knot_count.size();
+  hipError_t e = hipMalloc((void**)&tp->ckpt, st * tp->n_ckpt);
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->seg, st * tp->K);
+  for (double** b : {&tp->V, &tp->Ui, &tp->lam, &tp->nu1, &tp->nu2})
+    if (e == hipSuccess) e = hipMalloc((void**)b, st);
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->gman, c->n * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->gq, (size_t)n_steps * 2 * std::max(nseg, 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->gh, (size_t)(n_steps + 1) * std::max(n_gauges, 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->dj, (size_t)(n_steps + 1) * std::max(n_gauges, 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->gidx, std::max(n_gauges, 1) * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->regime, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->ctrl, sizeof(dg2k::Ctrl));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->ledger, (size_t)c->L.n_tiles * 4 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->d_t, (size_t)(n_steps + 1) * sizeof(double));
+  if (e == hipSuccess && n_gauges > 0)
+    e = hipMemcpyAsync(tp->gidx, gauges, n_gauges * sizeof(int), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    g_init_err = std::string("tape buffers: ") + hipGetErrorString(e);
+    dg2_tape_destroy(tp);
+    return DG2_E_DEVICE;
+  }
+  *out = tp;
+  return DG2_OK;
+}
+
+int dg2_tape_forward(dg2_tape* tp, double* gauge_h) {
+  if (!tp) return DG2_E_ARG;
+  dg2_ctx* c = tp->c;
+  const size_t st = 9 * c->n * sizeof(double);
+  int rc = pull_ctrl(c);
+  if (rc) return tfail(tp, rc, "%s", c->err.c_str());
+  tp->t.assign(tp->n_steps + 1, 0.0);
+  tp->t[0] = c->h_ctrl->t[c->parity];
+  for (int k = 0; k < tp->n_steps; ++k) tp->t[k + 1] = tp->t[k] + tp->dts[k];
+  THIPC(tp, hipMemcpyAsync(tp->d_t, tp->t.data(), tp->t.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  const unsigned gb = (unsigned)((tp->ng + 63) / 64);
+  auto cur = [&]() { return reinterpret_cast<double*>(c->ws + (c->parity ? c->L.u1 : c->L.u0)); };
+  if (tp->ng > 0) hipLaunchKernelGGL(dg2k::gauge_read_kernel, dim3(gb), dim3(64), 0, c->stream, cur(), tp->gidx, tp->ng, tp->gh);
+  for (int k = 0; k < tp->n_steps; ++k) {
+    if (k % tp->K == 0)
+      THIPC(tp, hipMemcpyAsync(tp->ckpt + (size_t)(k / tp->K) * 9 * c->n, cur(), st, hipMemcpyDeviceToDevice, c->stream));
+    c->dt_fix = tp->dts[k];
+    rc = step_any(c, 0.0, INFINITY);
+    c->dt_fix = 0.0;
+    if (rc) return tfail(tp, rc, "%s", c->err.c_str());
+    if (tp->ng > 0)
+      hipLaunchKernelGGL(dg2k::gauge_read_kernel, dim3(gb), dim3(64), 0, c->stream, cur(), tp->gidx, tp->ng,
+                         tp->gh + (size_t)(k + 1) * tp->ng);
+  }
+  THIPC(tp, hipGetLastError());
+  if ((rc = pull_ctrl(c))) return tfail(tp, rc, "%s", c->err.c_str());
+  if ((rc = check_health(c))) return tfail(tp, rc, "%s", c->err.c_str());
+  if (gauge_h && tp->ng > 0)
+    THIPC(tp, hipMemcpy(gauge_h, tp->gh, (size_t)(tp->n_steps + 1) * tp->ng * sizeof(double), hipMemcpyDeviceToHost));
+  tp->recorded = true;
+  return DG2_OK;
+}
+
+int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, double* grad_q,
+                      double* grad_u0) {
+  if (!tp || (tp->ng > 0 && !dj_dh)) return DG2_E_ARG;
+  if (!tp->recorded) return tfail(tp, DG2_E_STATE, "no forward run recorded");
+  dg2_ctx* c = tp->c;
+  hipStream_t sm = c->stream;
+  const long long n = (long long)c->n, m9 = 9 * n;
+  const size_t st = 9 * c->n * sizeof(double);
+  const int nseg = (int)c->knot_count.size();
+  const unsigned eb = (unsigned)((m9 + 255) / 256), cb = (unsigned)((n + 255) / 256);
+  const unsigned gb = (unsigned)((tp->ng + 63) / 64);
+  // reset
+  {
+    dg2k::Ctrl ctrl{};
+    set_cands_inf(ctrl);
+    ctrl.step[0] = ctrl.step[1] = 0;
+    THIPC(tp, hipMemcpyAsync(tp->ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice, sm));
+    THIPC(tp, hipStreamSynchronize(sm));
+  }
+  THIPC(tp, hipMemsetAsync(tp->lam, 0, st, sm));
+  THIPC(tp, hipMemsetAsync(tp->gman, 0, c->n * sizeof(double), sm));
+  THIPC(tp, hipMemsetAsync(tp->gq, 0, (size_t)tp->n_steps * 2 * std::max(nseg, 1) * sizeof(double), sm));
+  THIPC(tp, hipMemsetAsync(tp->regime, 0, sizeof(int), sm));
+  if (tp->ng > 0) {
+    THIPC(tp, hipMemcpyAsync(tp->dj, dj_dh, (size_t)(tp->n_steps + 1) * tp->ng * sizeof(double),
+                             hipMemcpyHostToDevice, sm));
+    hipLaunchKernelGGL(dg2k::gauge_seed_kernel, dim3(gb), dim3(64), 0, sm, tp->lam, tp->gidx, tp->ng,
+                       tp->dj + (size_t)tp->n_steps * tp->ng);
+  }
+  int rc = DG2_OK;
+  for (int sgi = tp->n_ckpt - 1; sgi >= 0 && rc == DG2_OK; --sgi) {
+    const int s0 = sgi * tp->K, s1 = std::min(tp->n_steps, s0 + tp->K);
+    // recompute the segment's states from its checkpoint
+    THIPC(tp, hipMemcpyAsync(tp->seg, tp->ckpt + (size_t)sgi * m9, st, hipMemcpyDeviceToDevice, sm));
+    for (int k = s0; k < s1 - 1 && rc == DG2_OK; ++k) {
+      rc = tape_step(tp, tp->seg + (size_t)(k - s0) * m9, k, true);
+      if (rc == DG2_OK)
+        THIPC(tp, hipMemcpyAsync(tp->seg + (size_t)(k - s0 + 1) * m9, tp->V, st, hipMemcpyDeviceToDevice, sm));
+    }
+    for (int k = s1 - 1; k >= s0 && rc == DG2_OK; --k) {
+      const double* U = tp->seg + (size_t)(k - s0) * m9;
+      const double dt = tp->dts[k];
+      if ((rc = tape_step(tp, U, k, false))) break;  // V^n, U^int
+      Params<double> p = params<double>(c);
+      dg2k::AdjArgs a2{tp->Ui, tp->lam, 0.5 * dt, tp->t[k] + dt, tp->nu2,
+                       tp->gq + ((size_t)k * 2 + 1) * std::max(nseg, 1), tp->regime};
+      hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(256), 0, sm, p, a2);
+      hipLaunchKernelGGL(dg2k::adj_combine_kernel, dim3(eb), dim3(256), 0, sm, m9, tp->lam, tp->nu2,
+                         (const double*)nullptr, 0.5);
+      dg2k::AdjArgs a1{tp->V, tp->nu2, dt, tp->t[k], tp->nu1,
+                       tp->gq + ((size_t)k * 2) * std::max(nseg, 1), tp->regime};
+      hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(256), 0, sm, p, a1);
+      hipLaunchKernelGGL(dg2k::adj_combine_kernel, dim3(eb), dim3(256), 0, sm, m9, tp->lam, tp->nu1,
+                         (const double*)tp->nu2, 0.5);
+      hipLaunchKernelGGL(dg2k::adj_friction_kernel, dim3(cb), dim3(256), 0, sm, p, U, tp->nu1, dt, tp->lam,
+                         tp->gman);
+      if (tp->ng > 0)
+        hipLaunchKernelGGL(dg2k::gauge_seed_kernel, dim3(gb), dim3(64), 0, sm, tp->lam, tp->gidx, tp->ng,
+                           tp->dj + (size_t)k * tp->ng);
+      THIPC(tp, hipGetLastError());
+    }
+  }
+  if (rc) return rc;
+  int regime = 0, health = 0;
+  THIPC(tp, hipMemcpyAsync(&regime, tp->regime, sizeof(int), hipMemcpyDeviceToHost, sm));
+  THIPC(tp, hipMemcpyAsync(&health, &tp->ctrl->health, sizeof(int), hipMemcpyDeviceToHost, sm));
+  THIPC(tp, hipStreamSynchronize(sm));
+  if (health & 1) return tfail(tp, DG2_E_NUMERIC, "NaN in a recomputed state");
+  if (regime)
+    return tfail(tp, DG2_E_UNSUPPORTED, "the run leaves the adjoint's regime (%s%s)",
+                 (regime & 1) ? "a dry cell or face" : "", (regime & 2) ? " a binding velocity cap" : "");
+  if (grad_manning) THIPC(tp, hipMemcpy(grad_manning, tp->gman, c->n * sizeof(double), hipMemcpyDeviceToHost));
+  if (grad_u0) THIPC(tp, hipMemcpy(grad_u0, tp->lam, st, hipMemcpyDeviceToHost));
+  if (grad_q && nseg > 0) {
+    std::vector<double> gq((size_t)tp->n_steps * 2 * nseg);
+    THIPC(tp, hipMemcpy(gq.data(), tp->gq, gq.size() * sizeof(double), hipMemcpyDeviceToHost));
+    // knots of every inflow segment (host copy of the device table)
+    std::vector<double> kn(2 * DG2_MAX_KNOTS);
+    THIPC(tp, hipMemcpy(kn.data(), c->ws + c->L.knots, kn.size() * sizeof(double), hipMemcpyDeviceToHost));
+    int k0 = 0, out0 = 0;
+    for (int sg = 0; sg < nseg; ++sg) {
+      const int nk = c->knot_count[sg];
+      for (int q = 0; q < nk; ++q) grad_q[out0 + q] = 0.0;
+      const double* kt = kn.data() + k0;
+      for (int k = 0; k < tp->n_steps && nk > 0; ++k)
+        for (int stg = 0; stg < 2; ++stg) {
+          const double tq = stg == 0 ? tp->t[k] : tp->t[k] + tp->dts[k];
+          const double gv = gq[((size_t)k * 2 + stg) * nseg + sg];
+          if (gv == 0.0) continue;
+          // Q(t) is linear between knots and held outside them (as in the kernels)
+          if (tq <= kt[0]) { grad_q[out0] += gv; continue; }
+          if (tq >= kt[nk - 1]) { grad_q[out0 + nk - 1] += gv; continue; }
+          int j = 0;
+          while (j + 1 < nk && kt[j + 1] <= tq) ++j;
+          const double w = (tq - kt[j]) / (kt[j + 1] - kt[j]);
+          grad_q[out0 + j] += (1.0 - w) * gv;
+          grad_q[out0 + j + 1] += w * gv;
+        }
+      k0 += nk;
+      out0 += nk;
+    }
+  }
+  return DG2_OK;
+}
+
+const char* dg2_tape_last_error(const dg2_tape* tp) { return tp ? tp->err.c_str() : g_init_err.c_str(); }
+
+void dg2_tape_destroy(dg2_tape* tp) {
+  if (!tp) return;
+  (void)hipStreamSynchronize(tp->c->stream);
+  for (void* b : {(void*)tp->ckpt, (void*)tp->seg, (void*)tp->V, (void*)tp->Ui, (void*)tp->lam, (void*)tp->nu1,
+                  (void*)tp->nu2, (void*)tp->gman, (void*)tp->gq, (void*)tp->gh, (void*)tp->dj, (void*)tp->gidx,
+                  (void*)tp->regime, (void*)tp->ctrl, (void*)tp->ledger, (void*)tp->d_t})
+    if (b) (void)hipFree(b);
+  delete tp;
 }
 
 int dg2_bed_info(const dg2_ctx* c, double* quantum, double* max_local) {

@@ -102,6 +102,7 @@ struct Params {
   int nx, ny, tx, ty, tiles_x, n_tiles, per_xcd, nsegs, max_knots, limiter, parity, fv1;
   R dx, g, h_tol, n_scalar;
   double dxd, gd, cfl, htd, dt_dry, dt_max, t_end;
+  double dt_fix;               // > 0: the step takes exactly this dt (a replayed schedule)
 };
 
 template <typename R> struct K;
@@ -218,6 +219,11 @@ __device__ __forceinline__ void step_time(const Params<R>& p, double& t, double&
   const double m = cand_read(p.ctrl->dtc[p.parity]);
   double d = (m == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * m;
   dt_cfl = d;
+  if (p.dt_fix > 0.0) {
+    dt = p.dt_fix;
+    t_next = t + dt;
+    return;
+  }
   if (p.dt_max > 0.0 && p.dt_max < d) d = p.dt_max;
   t_next = t + d;
   if (p.t_end - t <= d) {

@@ -25,6 +25,8 @@ SYMBOLS = ("dg2_workspace_size", "dg2_init", "dg2_step", "dg2_run", "dg2_read",
            "dg2_bed_info", "dg2_plan_bed_datum", "dg2_tile_shapes", "dg2_tile_grid",
            "dg2_batch_create",
            "dg2_batch_step", "dg2_batch_run", "dg2_batch_last_error", "dg2_batch_destroy",
+           "dg2_set_manning", "dg2_set_hydrograph", "dg2_tape_create", "dg2_tape_forward",
+           "dg2_tape_backward", "dg2_tape_last_error", "dg2_tape_destroy",
            "dg2_last_error", "dg2_init_error", "dg2_destroy")
 
 _dp = C.POINTER(C.c_double)
@@ -97,6 +99,15 @@ def load(path: str = LIB_PATH):
     lib.dg2_batch_last_error.restype = C.c_char_p
     lib.dg2_batch_destroy.argtypes = [vp]
     lib.dg2_batch_destroy.restype = None
+    lib.dg2_set_manning.argtypes = [vp, _dp]
+    lib.dg2_set_hydrograph.argtypes = [vp, i32, _dp]
+    lib.dg2_tape_create.argtypes = [vp, i32, _dp, C.POINTER(i32), i32, i32, C.POINTER(vp)]
+    lib.dg2_tape_forward.argtypes = [vp, _dp]
+    lib.dg2_tape_backward.argtypes = [vp, _dp, _dp, _dp, _dp]
+    lib.dg2_tape_last_error.argtypes = [vp]
+    lib.dg2_tape_last_error.restype = C.c_char_p
+    lib.dg2_tape_destroy.argtypes = [vp]
+    lib.dg2_tape_destroy.restype = None
     _lib = lib
     return lib
 
@@ -292,6 +303,14 @@ class DG2:
         self._check(self._lib.dg2_get_timing(self._h, C.byref(s), C.byref(a), C.byref(b)))
         return dict(steps=s.value, ms_stage1=a.value, ms_stage2=b.value)
 
+    def set_manning(self, manning: np.ndarray) -> None:
+        m = _f64(manning).reshape(-1)
+        self._check(self._lib.dg2_set_manning(self._h, _ptr(m)))
+
+    def set_hydrograph(self, seg: int, q_knots: np.ndarray) -> None:
+        q = _f64(q_knots).reshape(-1)
+        self._check(self._lib.dg2_set_hydrograph(self._h, int(seg), _ptr(q)))
+
     def bed_info(self) -> dict:
         q, b = C.c_double(), C.c_double()
         self._check(self._lib.dg2_bed_info(self._h, C.byref(q), C.byref(b)))
@@ -343,3 +362,83 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+class Tape:
+    """A recorded forward run of a DG2 simulation (FP64, limiter off, fully wet) with
+    prescribed time steps, and the discrete adjoint of that run."""
+
+    def __init__(self, sim: DG2, dts, gauges, checkpoint_every: int = 0):
+        lib = load()
+        self._lib = lib
+        self.sim = sim
+        self.dts = _f64(dts).reshape(-1)
+        self.gauges = np.ascontiguousarray(gauges, dtype=np.int32).reshape(-1)
+        self.n_steps, self.ng = len(self.dts), len(self.gauges)
+        h = C.c_void_p()
+        rc = lib.dg2_tape_create(sim._h, self.n_steps, _ptr(self.dts),
+                                 self.gauges.ctypes.data_as(C.POINTER(C.c_int32)), self.ng,
+                                 int(checkpoint_every), C.byref(h))
+        if rc != 0:
+            raise DG2Error(rc, lib.dg2_tape_last_error(None).decode())
+        self._h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise DG2Error(rc, self._lib.dg2_tape_last_error(self._h).decode())
+
+    def forward(self) -> np.ndarray:
+        """Run the schedule; returns the gauge depths, (n_steps + 1) x n_gauges."""
+        out = np.empty((self.n_steps + 1, self.ng))
+        self._check(self._lib.dg2_tape_forward(self._h, _ptr(out)))
+        return out
+
+    def backward(self, dj_dh: np.ndarray, n_knots: int):
+        """dJ/d(gauge depths) -> (dJ/dn per cell, dJ/dq per knot, dJ/dU0)."""
+        dj = _f64(dj_dh).reshape(self.n_steps + 1, self.ng)
+        gm = np.empty(self.sim.ny * self.sim.nx)
+        gq = np.empty(max(n_knots, 1))
+        gu = np.empty(9 * self.sim.ny * self.sim.nx)
+        self._check(self._lib.dg2_tape_backward(self._h, _ptr(dj), _ptr(gm), _ptr(gq), _ptr(gu)))
+        return (gm.reshape(self.sim.ny, self.sim.nx), gq[:n_knots],
+                gu.reshape(9, self.sim.ny, self.sim.nx))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.dg2_tape_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def gauge_run_function():
+    """A torch.autograd.Function: (manning per cell, knots of segment 0) -> gauge depths
+    over a recorded run, differentiated by the library's adjoint. Call as
+    f.apply(manning, q_knots, sim, dts, gauges, state0) with state0 the initial state
+    blob (the simulation is reset to it before each forward)."""
+    import torch
+
+    class GaugeRun(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, manning, q_knots, sim, dts, gauges, state0):
+            sim.set_state(state0)
+            sim.set_manning(manning.detach().cpu().numpy())
+            sim.set_hydrograph(0, q_knots.detach().cpu().numpy())
+            tape = Tape(sim, dts, gauges)
+            gh = tape.forward()
+            ctx.tape = tape
+            ctx.n_knots = int(q_knots.numel())
+            ctx.shapes = (manning.shape, manning.dtype, manning.device)
+            return torch.as_tensor(gh, dtype=manning.dtype, device=manning.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            gm, gq, _ = ctx.tape.backward(g.detach().cpu().numpy(), ctx.n_knots)
+            ctx.tape.close()
+            shape, dtype, dev = ctx.shapes
+            return (torch.as_tensor(gm, dtype=dtype, device=dev).reshape(shape),
+                    torch.as_tensor(gq, dtype=dtype, device=dev), None, None, None, None)
+
+    return GaugeRun
