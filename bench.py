@@ -12,7 +12,9 @@ depth error against the FP64 path, the same terrain as configured (dry start, ch
 inflow hydrograph) timed from a snapshot at t = 3600 s, the urban precision run (FP32
 with per-tile bed datums against FP64: depth error, mass drift, also with the bed raised
 by 1000 m), the batched run of 64 uneven scenarios against running them one at a
-time, the stage-kernel durations from HIP events recorded on the launch stream
+time, the adjoint leg (gradients of a gauge misfit on a 512x512 fully wet flow, 2000
+steps, against finite differences; adjoint time over forward time), the stage-kernel
+durations from HIP events recorded on the launch stream
 with the roofline of the dominant kernel, and the FP64 CPU oracle timed on this host's
 cores on a bounded sample.
 """
@@ -119,6 +121,79 @@ def fv1_leg(dg2, S, n, steps, warmup):
                     "algorithmic_bytes_per_launch": bytes_,
                     "roofline_frac": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     return out
+
+
+def adjoint_leg(dg2, S, n, steps, n_gauges=32):
+    """Gradients of a gauge misfit through the discrete adjoint: a fully wet, limiter-off
+    flow on an n x n fBm terrain (dx 5 m) with Manning n in 16 zones and a 48-knot inflow
+    hydrograph, `steps` RK2 steps on a replayed schedule (0.8 of the CFL steps of a plain
+    run), misfit against a run with every zone value raised by 20 %. Times the plain
+    forward, the recorded forward and the adjoint, and checks two zone and two knot
+    gradients against central differences of the misfit (steps of 1e-4 relative)."""
+    import torch
+    sc = S.adjoint_case(n=n, dx=5.0, t_span=200.0, n_knots=48)
+    rng = np.random.default_rng(5)
+    gi = rng.choice(n * n, size=n_gauges, replace=False)
+    probe = dg2.DG2(sc, dg2.FP64)
+    dts = np.array([0.8 * probe.step() for _ in range(steps)])
+    del probe
+    zi = S.zone_index(n, 4)
+    nz0 = np.array([sc.manning.reshape(-1)[zi.reshape(-1) == z][0] for z in range(16)])
+    q0 = np.asarray(sc.boundaries[0].q_knots, dtype=np.float64)
+
+    def run(manning=None, q=None, record=True):
+        sim = dg2.DG2(sc, dg2.FP64)
+        if manning is not None:
+            sim.set_manning(manning)
+        if q is not None:
+            sim.set_hydrograph(0, q)
+        tape = dg2.Tape(sim, dts, gi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = tape.forward()
+        return sim, tape, h, time.perf_counter() - t0
+
+    _, _, href, _ = run(manning=(nz0 * 1.2)[zi])
+    # plain forward with the same schedule (no tape)
+    plain = dg2.DG2(sc, dg2.FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for dt in dts:
+        plain.step(dt_max=float(dt), sync=False)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    sim, tape, h, t_fwd = run()
+    J = float(((h - href) ** 2).sum())
+    t0 = time.perf_counter()
+    gm, gq, _ = tape.backward(2.0 * (h - href), len(q0))
+    t_bwd = time.perf_counter() - t0
+    gz = np.array([gm.reshape(-1)[zi.reshape(-1) == z].sum() for z in range(16)])
+
+    def misfit(manning=None, q=None):
+        return float(((run(manning=manning, q=q)[2] - href) ** 2).sum())
+
+    checks = {}
+    for z in (0, 5):
+        e = 1e-4 * nz0[z]
+        p_, m_ = nz0.copy(), nz0.copy()
+        p_[z] += e
+        m_[z] -= e
+        fd = (misfit(manning=p_[zi]) - misfit(manning=m_[zi])) / (2 * e)
+        checks[f"zone{z}"] = {"adjoint": float(gz[z]), "fd": fd}
+    for k in (10, 30):
+        e = 1e-4 * q0[k]
+        p_, m_ = q0.copy(), q0.copy()
+        p_[k] += e
+        m_[k] -= e
+        fd = (misfit(q=p_) - misfit(q=m_)) / (2 * e)
+        checks[f"knot{k}"] = {"adjoint": float(gq[k]), "fd": fd}
+    worst = max(abs(c["adjoint"] - c["fd"]) / max(abs(c["fd"]), 1e-300) for c in checks.values())
+    return {"workload": f"fully wet fBm {n}x{n}, dx 5 m, 16 Manning zones, 48-knot inflow, "
+                        f"{steps} steps, {n_gauges} gauges, FP64",
+            "misfit": J, "checkpoint_every": int(np.ceil(np.sqrt(steps))),
+            "seconds": {"forward_plain": t_plain, "forward_recorded": t_fwd, "adjoint": t_bwd},
+            "adjoint_over_forward": t_bwd / t_plain,
+            "fd_checks": checks, "max_rel_diff_vs_fd": worst}
 
 
 def precision_form(dg2, S, n, t_end):
@@ -231,6 +306,8 @@ def main():
     ap.add_argument("--t-urban", type=float, default=600.0, help="simulated seconds of the urban run")
     ap.add_argument("--batch-count", type=int, default=64, help="scenarios in the batched run")
     ap.add_argument("--batch-t-end", type=float, default=1800.0, help="simulated seconds per scenario")
+    ap.add_argument("--adjoint-n", type=int, default=512, help="grid side of the adjoint leg")
+    ap.add_argument("--adjoint-steps", type=int, default=2000, help="RK2 steps of the adjoint leg")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the FP64 timed region (for profiler runs)")
     ap.add_argument("--fv1-only", action="store_true",
@@ -358,6 +435,12 @@ def main():
               f"({bt['seconds']:.1f} s), one at a time {bt['one_at_a_time']['value']:.4g} "
               f"({bt['one_at_a_time']['seconds']:.1f} s), bitwise equal: "
               f"{bt['bitwise_equal_to_one_at_a_time']}", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_leg(dg2, S, args.adjoint_n, args.adjoint_steps)
+        ad = out["adjoint"]
+        print(f"[bench] adjoint {args.adjoint_n}^2 x {args.adjoint_steps} steps: forward "
+              f"{ad['seconds']['forward_plain']:.3f} s, adjoint {ad['seconds']['adjoint']:.3f} s "
+              f"({ad['adjoint_over_forward']:.1f}x), max rel diff vs FD {ad['max_rel_diff_vs_fd']:.1e}",
+              file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
         print(f"[bench] CPU oracle {out['cpu_baseline']['value']:.4g} cell-updates/s on "
               f"{out['cpu_baseline']['cores']} threads", file=sys.stderr, flush=True)

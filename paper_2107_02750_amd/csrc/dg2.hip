@@ -127,6 +127,7 @@ struct dg2_ctx {
   bool in_batch;       // borrowed by a batch: not stepped alone
   double dt_fix;       // > 0: the next steps take exactly this dt (a tape's schedule)
   std::vector<int> knot_count;  // hydrograph knots of each boundary segment
+  std::vector<int> seg_edge, seg_i0, seg_i1;  // each boundary segment's faces
   std::string err;
 };
 
@@ -828,7 +829,12 @@ int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, dou
   x->t_ms1 = x->t_ms2 = 0;
   x->in_batch = false;
   x->dt_fix = 0.0;
-  for (int s = 0; s < n_bcs; ++s) x->knot_count.push_back(bcs[s].kind == DG2_BC_INFLOW ? bcs[s].n_knots : 0);
+  for (int s = 0; s < n_bcs; ++s) {
+    x->knot_count.push_back(bcs[s].kind == DG2_BC_INFLOW ? bcs[s].n_knots : 0);
+    x->seg_edge.push_back(bcs[s].edge);
+    x->seg_i0.push_back(bcs[s].i0);
+    x->seg_i1.push_back(bcs[s].i1);
+  }
   auto dev = [&](hipError_t e, const char* what) {
     if (e == hipSuccess) return false;
     g_init_err = std::string(what) + ": " + hipGetErrorString(e);
@@ -1166,7 +1172,7 @@ struct dg2_tape {
   double* nu1;
   double* nu2;
   double* gman;                // dJ/dn per cell
-  double* gq;                  // dJ/dQ(t) per (step, stage, segment)
+  double* gq;                  // dJ/dQ(t) per (step, stage, boundary face slot)
   double* gh;                  // gauge depths (n_steps + 1) x ng
   double* dj;                  // dJ/dh on the device
   int* gidx;
@@ -1279,13 +1285,13 @@ int dg2_tape_create(dg2_ctx* c, int32_t n_steps, const double* dts, const int32_
   tp->dts.assign(dts, dts + n_steps);
   tp->recorded = false;
   const size_t st = 9 * c->n * sizeof(double);
-  int nseg = (int)c->knot_count.size();
+  const size_t nfs = 2 * ((size_t)c->cfg.nx + c->cfg.ny);  // boundary face slots
   hipError_t e = hipMalloc((void**)&tp->ckpt, st * tp->n_ckpt);
   if (e == hipSuccess) e = hipMalloc((void**)&tp->seg, st * tp->K);
   for (double** b : {&tp->V, &tp->Ui, &tp->lam, &tp->nu1, &tp->nu2})
     if (e == hipSuccess) e = hipMalloc((void**)b, st);
   if (e == hipSuccess) e = hipMalloc((void**)&tp->gman, c->n * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&tp->gq, (size_t)n_steps * 2 * std::max(nseg, 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->gq, (size_t)n_steps * 2 * nfs * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->gh, (size_t)(n_steps + 1) * std::max(n_gauges, 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->dj, (size_t)(n_steps + 1) * std::max(n_gauges, 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->gidx, std::max(n_gauges, 1) * sizeof(int));
@@ -1347,6 +1353,7 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
   const long long n = (long long)c->n, m9 = 9 * n;
   const size_t st = 9 * c->n * sizeof(double);
   const int nseg = (int)c->knot_count.size();
+  const size_t nfs = 2 * ((size_t)c->cfg.nx + c->cfg.ny);
   const unsigned eb = (unsigned)((m9 + 255) / 256), cb = (unsigned)((n + 255) / 256);
   const unsigned gb = (unsigned)((tp->ng + 63) / 64);
   // reset
@@ -1359,7 +1366,7 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
   }
   THIPC(tp, hipMemsetAsync(tp->lam, 0, st, sm));
   THIPC(tp, hipMemsetAsync(tp->gman, 0, c->n * sizeof(double), sm));
-  THIPC(tp, hipMemsetAsync(tp->gq, 0, (size_t)tp->n_steps * 2 * std::max(nseg, 1) * sizeof(double), sm));
+  THIPC(tp, hipMemsetAsync(tp->gq, 0, (size_t)tp->n_steps * 2 * nfs * sizeof(double), sm));
   THIPC(tp, hipMemsetAsync(tp->regime, 0, sizeof(int), sm));
   if (tp->ng > 0) {
     THIPC(tp, hipMemcpyAsync(tp->dj, dj_dh, (size_t)(tp->n_steps + 1) * tp->ng * sizeof(double),
@@ -1383,12 +1390,12 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
       if ((rc = tape_step(tp, U, k, false))) break;  // V^n, U^int
       Params<double> p = params<double>(c);
       dg2k::AdjArgs a2{tp->Ui, tp->lam, 0.5 * dt, tp->t[k] + dt, tp->nu2,
-                       tp->gq + ((size_t)k * 2 + 1) * std::max(nseg, 1), tp->regime};
+                       tp->gq + ((size_t)k * 2 + 1) * nfs, tp->regime};
       hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(256), 0, sm, p, a2);
       hipLaunchKernelGGL(dg2k::adj_combine_kernel, dim3(eb), dim3(256), 0, sm, m9, tp->lam, tp->nu2,
                          (const double*)nullptr, 0.5);
       dg2k::AdjArgs a1{tp->V, tp->nu2, dt, tp->t[k], tp->nu1,
-                       tp->gq + ((size_t)k * 2) * std::max(nseg, 1), tp->regime};
+                       tp->gq + ((size_t)k * 2) * nfs, tp->regime};
       hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(256), 0, sm, p, a1);
       hipLaunchKernelGGL(dg2k::adj_combine_kernel, dim3(eb), dim3(256), 0, sm, m9, tp->lam, tp->nu1,
                          (const double*)tp->nu2, 0.5);
@@ -1412,8 +1419,17 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
   if (grad_manning) THIPC(tp, hipMemcpy(grad_manning, tp->gman, c->n * sizeof(double), hipMemcpyDeviceToHost));
   if (grad_u0) THIPC(tp, hipMemcpy(grad_u0, tp->lam, st, hipMemcpyDeviceToHost));
   if (grad_q && nseg > 0) {
-    std::vector<double> gq((size_t)tp->n_steps * 2 * nseg);
-    THIPC(tp, hipMemcpy(gq.data(), tp->gq, gq.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> gqf((size_t)tp->n_steps * 2 * nfs);
+    THIPC(tp, hipMemcpy(gqf.data(), tp->gq, gqf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    // per (step, stage, segment): the segment's faces summed in order
+    const size_t eoff[4] = {0, (size_t)c->cfg.ny, 2 * (size_t)c->cfg.ny, 2 * (size_t)c->cfg.ny + c->cfg.nx};
+    std::vector<double> gq((size_t)tp->n_steps * 2 * nseg, 0.0);
+    for (size_t ks = 0; ks < (size_t)tp->n_steps * 2; ++ks)
+      for (int sg = 0; sg < nseg; ++sg) {
+        double v = 0.0;
+        for (int f = c->seg_i0[sg]; f < c->seg_i1[sg]; ++f) v += gqf[ks * nfs + eoff[c->seg_edge[sg]] + f];
+        gq[ks * nseg + sg] = v;
+      }
     // knots of every inflow segment (host copy of the device table)
     std::vector<double> kn(2 * DG2_MAX_KNOTS);
     THIPC(tp, hipMemcpy(kn.data(), c->ws + c->L.knots, kn.size() * sizeof(double), hipMemcpyDeviceToHost));

@@ -268,7 +268,8 @@ struct AdjArgs {
   double alpha;
   double t;            // stage time (inflow discharge)
   double* nu;          // out: 9 planes
-  double* gq;          // out: += dJ/dQ per boundary segment (stage)
+  double* gqf;         // out: dJ/dQ of each inflow boundary face (slots as the face
+                       // codes: W[ny], E[ny], S[nx], N[nx]), summed per segment later
   int* regime;         // out: |= violation bits
 };
 
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     const double ucap = fmax(fabs(umean(c, true)), fabs(umean(nk, true))) + slack;
     const double vcap_ = fmax(fabs(umean(c, false)), fabs(umean(nk, false))) + slack;
     const DSide<4> own = drevise<4>(h, qx, qy, zf, zf, ht, ucap, vcap_, &bad);
-    int qseg = -1;  // inflow segment of this face, if any
+    int qslot = -1;  // face slot of an inflow face
     if (!(own.h.v > 0.0)) bad |= 1;
     DSide<4> nb;
     if (inside) {
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
         gut = dconst<4>(xdir ? s.v_b : s.u_b);
       } else if (kind == 3) {
         const Seg& s = p.segs[(code >> 8) - 1];
-        qseg = (code >> 8) - 1;
+        qslot = xdir ? (f == 0 ? 0 : ny) + j : 2 * ny + (f == 2 ? 0 : nx) + i;
         const Dual<4> Q = dvar<4>(hydrograph(s, p.knots, p.knots + p.max_knots, a.t), 3);
         const Dual<4> qn = Q * (1.0 / s.width);
         const Dual<4> hc = dcbrtd(qn * qn * (1.0 / g));
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     Dual<4> J = mt[0] * Fs[0] + mt[1] * Fs[1] + mt[2] * Fs[2];
 #pragma unroll
     for (int k = 0; k < 3; ++k) gface[f][k] = J.d[k];
-    if (qseg >= 0 && J.d[3] != 0.0) atomicAdd(&a.gq[qseg], J.d[3]);
+    if (qslot >= 0) a.gqf[qslot] = J.d[3];
   }
 
   // local terms of the cell's own L (Gauss fluxes and bed source), per direction
