@@ -42,28 +42,32 @@ def stage_bytes(n_cells, real_bytes):
 
 
 def kernel_source_hash():
+    """sha256 of what the forward kernels are compiled from: their source and the
+    build script that holds the compiler flags."""
     import hashlib
-    import glob
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2107_02750_amd", "csrc", "*"))):
+    for f in (os.path.join(ROOT, "paper_2107_02750_amd", "csrc", "dg2_kernels.hpp"),
+              os.path.join(ROOT, "paper_2107_02750_amd", "build.py")):
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel, precision_tag, n):
-    """HBM bytes per launch of a stage kernel from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None
-    when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles",
-                        f"traffic_stage_kernels_fbm_channel_wet_{n}_{precision_tag}.json")
+def measured_traffic(summary, kernel):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter summary
+    (profiles/<summary>.json: FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by
+    what they read for a plain copy of known size), or None when the kernel sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", summary + ".json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    k = rec["kib_per_dispatch"][kernel]
+    k = rec["kib_per_dispatch"].get(kernel)
+    if k is None:
+        return None
     sc = rec["copy_scale"]
     return 1024.0 * (k["fetch"] * sc["fetch"] + k["write"] * sc["write"])
 
@@ -119,7 +123,8 @@ def fv1_leg(dg2, S, n, steps, warmup):
         bytes_ = 7 * rb * n * n
         out[tag] = {"value": n * n * steps / el, "unit": "cell-updates/s", "ms_per_launch": ms,
                     "algorithmic_bytes_per_launch": bytes_,
-                    "roofline_frac": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                    "roofline_frac": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "traffic": measured_traffic(f"traffic_fv1_kernel_fbm_channel_wet_{n}", tag)}
     return out
 
 
@@ -377,7 +382,8 @@ def main():
                    "blocks_per_launch": info["blocks"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, "fp64", args.n),
+                     "traffic": measured_traffic(
+                         f"traffic_stage_kernels_fbm_channel_wet_{args.n}_fp64", dom),
                      "ms_per_launch": {"stage1": ms1, "stage2": ms2},
                      "algorithmic_bytes_per_launch": stage_bytes(n_cells, 8)},
     }
