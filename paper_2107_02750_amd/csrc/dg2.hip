@@ -29,14 +29,14 @@ struct Layout {
   int shape, tx, ty, threads, tiles_x, tiles_y, n_tiles, per_xcd, grid;
 };
 
-const int (*shape_table(int precision))[2] {
+const int (*shape_table(int precision))[4] {
   return precision == DG2_FP32 ? dg2k::SHAPE32 : dg2k::SHAPE64;
 }
 
 // index of the configured tile shape, or -1 if it is not one of the built shapes
 int shape_index(const dg2_config& c) {
   if (c.tile_x == 0 && c.tile_y == 0) return 0;
-  const int (*t)[2] = shape_table(c.precision);
+  const int (*t)[4] = shape_table(c.precision);
   for (int k = 0; k < dg2k::N_SHAPES; ++k)
     if (t[k][0] == c.tile_x && t[k][1] == c.tile_y) return k;
   return -1;
@@ -45,10 +45,12 @@ int shape_index(const dg2_config& c) {
 // the K-th tile shape of precision R
 template <typename R, int K> struct ShapeOf;
 template <int K> struct ShapeOf<double, K> {
-  using type = dg2k::Shape<dg2k::SHAPE64[K][0], dg2k::SHAPE64[K][1]>;
+  using type = dg2k::Shape<dg2k::SHAPE64[K][0], dg2k::SHAPE64[K][1], dg2k::SHAPE64[K][2],
+                           dg2k::SHAPE64[K][3]>;
 };
 template <int K> struct ShapeOf<float, K> {
-  using type = dg2k::Shape<dg2k::SHAPE32[K][0], dg2k::SHAPE32[K][1]>;
+  using type = dg2k::Shape<dg2k::SHAPE32[K][0], dg2k::SHAPE32[K][1], dg2k::SHAPE32[K][2],
+                           dg2k::SHAPE32[K][3]>;
 };
 
 // call F<R, shape>::run(args...) for the shape with index k
@@ -1068,7 +1070,7 @@ int dg2_get_timing(dg2_ctx* c, int64_t* steps, double* ms1, double* ms2) {
 
 int dg2_tile_shapes(int32_t precision, int32_t* xy, int32_t cap, int32_t* count) {
   if (precision != DG2_FP64 && precision != DG2_FP32) return DG2_E_ARG;
-  const int (*t)[2] = shape_table(precision);
+  const int (*t)[4] = shape_table(precision);
   if (count) *count = dg2k::N_SHAPES;
   for (int k = 0; xy && k < dg2k::N_SHAPES && k < cap; ++k) {
     xy[2 * k] = t[k][0];

@@ -22,14 +22,17 @@ namespace dg2k {
 
 // Tile shapes (cells; x fastest in memory). A context picks one of the shapes listed
 // per precision; index 0 is the default. One block of TX * TY threads owns a tile.
-template <int TX_, int TY_, int MINB_ = 1>
+// B1 / B2: the blocks per CU that the stage-1 / stage-2 kernel is compiled to fit
+// (a register budget: 4 blocks of 4 waves leave 128 VGPRs per lane).
+template <int TX_, int TY_, int B1_ = 1, int B2_ = 1>
 struct Shape {
-  static constexpr int X = TX_, Y = TY_, MINB = MINB_;
+  static constexpr int X = TX_, Y = TY_, B1 = B1_, B2 = B2_;
 };
 constexpr int N_SHAPES = 4;
-// FP64: 32x8 (default), 16x16, 16x8, 64x4; FP32: 64x8 (default), 32x16, 32x8, 16x16
-constexpr int SHAPE64[N_SHAPES][2] = {{32, 8}, {16, 16}, {16, 8}, {64, 4}};
-constexpr int SHAPE32[N_SHAPES][2] = {{64, 8}, {32, 16}, {32, 8}, {16, 16}};
+// FP64: 32x8 (default), 16x16, 16x8, 64x4; FP32: 64x8 (default), 32x16, 32x8, 16x16;
+// columns: TX, TY, B1, B2
+constexpr int SHAPE64[N_SHAPES][4] = {{32, 8, 4, 4}, {16, 16, 4, 4}, {16, 8, 1, 1}, {64, 4, 1, 1}};
+constexpr int SHAPE32[N_SHAPES][4] = {{64, 8, 1, 1}, {32, 16, 1, 1}, {32, 8, 1, 1}, {16, 16, 1, 1}};
 
 // LDS geometry of a tile: the cell box has a 2-cell halo, the vertex box one more
 template <typename S>
@@ -121,14 +124,16 @@ __device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
 
 // Reciprocal, square root and h^(-1/3) for the inner loops: the hardware estimates
-// (about 23 correct bits for FP64) refined by Newton steps to full FP64 precision
-// (within a few ulp, not correctly rounded); FP32 uses the 1-ulp hardware results.
+// (relative errors measured on gfx950: 2^-24.4 for the FP64 reciprocal, 2^-24.2 for
+// the FP64 reciprocal square root, 2^-20 for the FP32-seeded cube root) refined to full
+// FP64 precision (within a few ulp, not correctly rounded); FP32 uses the 1-ulp
+// hardware results.
+// 1/d: with e = 1 - d r, 1/d = r / (1 - e) = r (1 + e + e^2 + ...); one third-order
+// step leaves an error of order e^3, far below an ulp
 __device__ __forceinline__ double frcp(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = __builtin_fma(-d, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-d, r, 1.0);
-  return __builtin_fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(d);
+  const double e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, __builtin_fma(e, e, e), r);
 }
 __device__ __forceinline__ float frcp(float d) { return __builtin_amdgcn_rcpf(d); }
 
@@ -145,28 +150,23 @@ __device__ __forceinline__ double fsqrt(double x) {
 }
 __device__ __forceinline__ float fsqrt(float x) { return x > 0.0f ? __builtin_sqrtf(x) : 0.0f; }
 
-// 1/sqrt(x) for x > 0: the hardware estimate and two Newton steps y <- y (3 - x y^2) / 2
+// 1/sqrt(x) for x > 0: with e = 1 - x y^2, x^(-1/2) = y (1 - e)^(-1/2)
+// = y (1 + e/2 + 3e^2/8 + ...); one third-order step from the hardware estimate
 __device__ __forceinline__ double frsq(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double hy = 0.5 * y;
-  double e = __builtin_fma(-x * y, y, 1.0);
-  y = __builtin_fma(hy, e, y);
-  hy = 0.5 * y;
-  e = __builtin_fma(-x * y, y, 1.0);
-  return __builtin_fma(hy, e, y);
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-x * y, y, 1.0);
+  return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
 }
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// y = h^(-1/3) for h > 0: a float log2/exp2 seed, then Newton on y^-3 = h,
-// y <- y (4 - h y^3) / 3, which doubles the correct bits each step
+// y = h^(-1/3) for h > 0: a float log2/exp2 seed, then with e = 1 - h y^3,
+// h^(-1/3) = y (1 - e)^(-1/3) = y (1 + e/3 + 2e^2/9 + ...); one third-order step
 __device__ __forceinline__ double finvcbrt(double h) {
   if (!(h >= 1e-30)) return 1.0 / cbrt(h);
   const float hf = float(h);
-  double y = double(__builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf(hf)));
-  const double third = 0.33333333333333333333;
-  y = y * (4.0 - h * (y * y * y)) * third;
-  y = y * (4.0 - h * (y * y * y)) * third;
-  return y;
+  const double y = double(__builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf(hf)));
+  const double e = __builtin_fma(-h, y * y * y, 1.0);
+  return __builtin_fma(y * e, __builtin_fma(e, 0.22222222222222222222, 0.33333333333333333333), y);
 }
 __device__ __forceinline__ float finvcbrt(float h) {
   if (!(h >= 1e-30f)) return 1.0f / cbrtf(h);
@@ -457,12 +457,21 @@ __device__ __forceinline__ double cand_read(const Cand& c) {
 // ---------------------------------------------------------------------------------
 template <typename R, typename S>
 struct Smem {
-  R c[6][Geo<S>::RB];   // planes 0-2: box means h0, qx0, qy0; later the face-side
-                        // states and then the face fluxes
-  R zv[Geo<S>::VB];     // bed vertices of the box
-  R z0[Geo<S>::RB];     // bed means of the box cells
-  R um[Geo<S>::RB];     // mean velocities (zero at or below h_tol)
-  R vm[Geo<S>::RB];
+  static constexpr int TX = Geo<S>::TX, TY = Geo<S>::TY;
+  static constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);  // x / y faces of the tile
+  R c[6][Geo<S>::RB];   // planes 0-2: box means h0, qx0, qy0; later the face-side states
+  union {
+    struct {
+      R zv[Geo<S>::VB];  // bed vertices of the box
+      R z0[Geo<S>::RB];  // bed means of the box cells
+      R um[Geo<S>::RB];  // mean velocities (zero at or below h_tol)
+      R vm[Geo<S>::RB];
+    };
+    struct {             // once the face sides are formed: the tile's face fluxes
+      R fx[3][NFX];      // x face f of tile row b at b * (TX + 1) + f
+      R fy[3][NFY];      // y face f of tile column a at f * TX + a
+    };
+  };
   unsigned char flag[Geo<S>::RB];  // 1: first-order (front) cell
   double red[Geo<S>::NT / 64][4];
 };
@@ -792,6 +801,20 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
       sy1 = k2s3 * hb1 * zb1;
     }
   }
+  // the own-cell parts of L go into the stage update now (w = va + dt Lg), so that
+  // neither they nor va stay live through the face phase; stage 1 publishes V^n here
+  R w[9];
+  {
+    const R c = -s3 * (R(1) / p.dx);
+    const R Lg[9] = {R(0), -c * gx[0], -c * gy[0], -sx0, -c * gx[1] - sx1, -c * gy[1],
+                     -sy0, -c * gx[2], -c * gy[2] - sy1};
+#pragma unroll
+    for (int q = 0; q < 9; ++q) w[q] = va[q] + dtr * Lg[q];
+    if (STAGE == 1 && active) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) (p.vbuf + q * n)[ck] = va[q];
+    }
+  }
   if (active) {  // s_c is no longer read: it now holds face data
     s_side[0 * RB + cpos] = se_.h;
     s_side[1 * RB + cpos] = se_.u;
@@ -816,10 +839,10 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   const double t_stage = STAGE == 1 ? t : t_next;
   double led_in = 0.0, led_out = 0.0, led_clip = 0.0;
   const double wflux = 0.5 * dt * p.dxd;  // ledger weight: RK2 half step times face width
-  R fw[3] = {R(0), R(0), R(0)}, fs[3] = {R(0), R(0), R(0)};
-  // x-face at index f between cells f-1 and f on row j; pos is the box position of f
-  auto xface = [&](int f, int j, int pos, const Side<R>& own_r, bool have_r, R out[3]) -> bool {
-    if (EDGE && (j >= ny || f > nx)) return false;
+  // x-face at index f between cells f-1 and f on row j; pos is the box position of f;
+  // slot is the face's place in the flux array
+  auto xface = [&](int f, int j, int pos, const Side<R>& own_r, bool have_r, int slot) {
+    if (EDGE && (j >= ny || f > nx)) return;
     R lh = R(0), lu = R(0), lv = R(0), rh = R(0), ru = R(0), rv = R(0);
     if (!EDGE || f > 0) {
       lh = s_side[0 * RB + pos - 1];
@@ -827,7 +850,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
       lv = s_side[2 * RB + pos - 1];
     }
     if (!EDGE || f < nx) {
-      if (!have_r) return false;
+      if (!have_r) return;
       rh = own_r.h; ru = own_r.u; rv = own_r.v;
     }
     if (EDGE && f == 0) {
@@ -835,7 +858,11 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
     } else if (EDGE && f == nx) {
       ghost(p, p.bface[ny + j], t_stage, true, R(-1), lh, lu, lv, rh, ru, rv);
     }
+    R out[3];
     hll(g, lh, lu, lv, rh, ru, rv, out);
+    sm.fx[0][slot] = out[0];
+    sm.fx[1][slot] = out[1];
+    sm.fx[2][slot] = out[2];
     if (EDGE && f == 0) {
       const double m = double(out[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
@@ -843,10 +870,9 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
       const double m = -double(out[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
     }
-    return true;
   };
-  auto yface = [&](int i, int f, int pos, const Side<R>& own_r, bool have_r, R out[3]) -> bool {
-    if (EDGE && (i >= nx || f > ny)) return false;
+  auto yface = [&](int i, int f, int pos, const Side<R>& own_r, bool have_r, int slot) {
+    if (EDGE && (i >= nx || f > ny)) return;
     R lh = R(0), lu = R(0), lv = R(0), rh = R(0), ru = R(0), rv = R(0);  // (h, normal v, tangential u)
     if (!EDGE || f > 0) {
       lh = s_side[3 * RB + pos - RX];
@@ -854,7 +880,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
       lv = s_side[4 * RB + pos - RX];
     }
     if (!EDGE || f < ny) {
-      if (!have_r) return false;
+      if (!have_r) return;
       rh = own_r.h; ru = own_r.v; rv = own_r.u;
     }
     if (EDGE && f == 0) {
@@ -864,9 +890,9 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
     }
     R o[3];
     hll(g, lh, lu, lv, rh, ru, rv, o);
-    out[0] = o[0];
-    out[1] = o[2];  // x-momentum is tangential on a y-face
-    out[2] = o[1];
+    sm.fy[0][slot] = o[0];
+    sm.fy[1][slot] = o[2];  // x-momentum is tangential on a y-face
+    sm.fy[2][slot] = o[1];
     if (EDGE && f == 0) {
       const double m = double(o[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
@@ -874,20 +900,13 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
       const double m = -double(o[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
     }
-    return true;
   };
   // own position (also the east / north boundary face when the cell is just outside)
-  const bool hw = xface(ci, cj, cpos, sw_, active, fw);
-  const bool hs = yface(ci, cj, cpos, ss_, active, fs);
-  R fb3[3] = {R(0), R(0), R(0)};
-  bool hb = false;
-  if (has_b && rb_side == 1) hb = xface(ri, rj, rpos, sb_, b_in, fb3);
-  if (has_b && rb_side == 3) hb = yface(ri, rj, rpos, sb_, b_in, fb3);
-  __syncthreads();  // side reads done; the same slots now receive fluxes
-  if (hw) { s_side[0 * RB + cpos] = fw[0]; s_side[1 * RB + cpos] = fw[1]; s_side[2 * RB + cpos] = fw[2]; }
-  if (hs) { s_side[3 * RB + cpos] = fs[0]; s_side[4 * RB + cpos] = fs[1]; s_side[5 * RB + cpos] = fs[2]; }
-  if (hb && rb_side == 1) { s_side[0 * RB + rpos] = fb3[0]; s_side[1 * RB + rpos] = fb3[1]; s_side[2 * RB + rpos] = fb3[2]; }
-  if (hb && rb_side == 3) { s_side[3 * RB + rpos] = fb3[0]; s_side[4 * RB + rpos] = fb3[1]; s_side[5 * RB + rpos] = fb3[2]; }
+  const int ta = tid % TX, tb = tid / TX;  // the thread's tile position
+  xface(ci, cj, cpos, sw_, active, tb * (TX + 1) + ta);
+  yface(ci, cj, cpos, ss_, active, tb * TX + ta);
+  if (has_b && rb_side == 1) xface(ri, rj, rpos, sb_, b_in, (rb_b - 2) * (TX + 1) + TX);
+  if (has_b && rb_side == 3) yface(ri, rj, rpos, sb_, b_in, TY * TX + (rb_a - 2));
   __syncthreads();
 
   // ---- phase 3: L, the stage update, and the per-block reductions ----
@@ -897,33 +916,39 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
 #pragma unroll
       for (int q = 0; q < 9; ++q) vn[q] = (p.vbuf + q * n)[ck];
     }
-    const R fe[3] = {s_side[0 * RB + cpos + 1], s_side[1 * RB + cpos + 1], s_side[2 * RB + cpos + 1]};
-    const R fn[3] = {s_side[3 * RB + cpos + RX], s_side[4 * RB + cpos + RX], s_side[5 * RB + cpos + RX]};
+    const int xw = tb * (TX + 1) + ta, ys = tb * TX + ta;
+    const R fw[3] = {sm.fx[0][xw], sm.fx[1][xw], sm.fx[2][xw]};
+    const R fe[3] = {sm.fx[0][xw + 1], sm.fx[1][xw + 1], sm.fx[2][xw + 1]};
+    const R fs[3] = {sm.fy[0][ys], sm.fy[1][ys], sm.fy[2][ys]};
+    const R fn[3] = {sm.fy[0][ys + TX], sm.fy[1][ys + TX], sm.fy[2][ys + TX]};
     const R idx = R(1) / p.dx;
     const R c = -s3 * idx;
     R L[9];
     L[0] = -(fe[0] - fw[0]) * idx + -(fn[0] - fs[0]) * idx;
-    L[3] = (-(fe[1] - fw[1]) * idx - sx0) + -(fn[1] - fs[1]) * idx;
-    L[6] = -(fe[2] - fw[2]) * idx + (-(fn[2] - fs[2]) * idx - sy0);
-    L[1] = c * (fe[0] + fw[0] - gx[0]);
-    L[4] = c * (fe[1] + fw[1] - gx[1]) - sx1;
-    L[7] = c * (fe[2] + fw[2] - gx[2]);
-    L[2] = c * (fn[0] + fs[0] - gy[0]);
-    L[5] = c * (fn[1] + fs[1] - gy[1]);
-    L[8] = c * (fn[2] + fs[2] - gy[2]) - sy1;
+    L[3] = -(fe[1] - fw[1]) * idx + -(fn[1] - fs[1]) * idx;
+    L[6] = -(fe[2] - fw[2]) * idx + -(fn[2] - fs[2]) * idx;
+    L[1] = c * (fe[0] + fw[0]);
+    L[4] = c * (fe[1] + fw[1]);
+    L[7] = c * (fe[2] + fw[2]);
+    L[2] = c * (fn[0] + fs[0]);
+    L[5] = c * (fn[1] + fs[1]);
+    L[8] = c * (fn[2] + fs[2]);
     R u[9];
     if (STAGE == 1) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) u[q] = va[q] + dtr * L[q];
+      for (int q = 0; q < 9; ++q) u[q] = w[q] + dtr * L[q];
     } else {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) u[q] = R(0.5) * (vn[q] + va[q] + dtr * L[q]);
+      for (int q = 0; q < 9; ++q) u[q] = R(0.5) * (vn[q] + w[q] + dtr * L[q]);
     }
     // after each stage: clip a negative mean depth (booking the mass), then drop the
     // discharge of cells at or below the dry tolerance
-    if (u[0] < R(0)) {
-      led_clip += -double(u[0]) * p.dxd * p.dxd * (STAGE == 1 ? 0.5 : 1.0);
-      u[0] = u[1] = u[2] = R(0);
+    {  // branch-free: a branch here splits the update and costs registers
+      const bool neg = u[0] < R(0);
+      led_clip = neg ? -double(u[0]) * p.dxd * p.dxd * (STAGE == 1 ? 0.5 : 1.0) : 0.0;
+      u[0] = neg ? R(0) : u[0];
+      u[1] = neg ? R(0) : u[1];
+      u[2] = neg ? R(0) : u[2];
     }
     const bool dry = !(u[0] > ht);
 #pragma unroll
@@ -934,10 +959,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
     if (sum != sum) atomicOr(&p.ctrl->health, 1);
     if (STAGE == 1) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        (p.vbuf + q * n)[ck] = va[q];
-        (p.ui + q * n)[ck] = u[q];
-      }
+      for (int q = 0; q < 9; ++q) (p.ui + q * n)[ck] = u[q];
     } else {
 #pragma unroll
       for (int q = 0; q < 9; ++q) (p.vbuf + q * n)[ck] = u[q];
@@ -945,19 +967,19 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
     }
   }
 
-  // per-block reductions in a fixed order (deterministic); ledger terms exist only in
-  // edge tiles (boundary fluxes) or where a depth was clipped
+  // per-block reductions in a fixed order (deterministic); boundary-flux ledger terms
+  // exist only in edge tiles
   const int lane = tid & 63, wv = tid >> 6;
-  const bool any_led = EDGE || __any(led_clip != 0.0);
-  if (any_led) {
-    const double r_in = wave_sum(led_in), r_out = wave_sum(led_out), r_clip = wave_sum(led_clip);
-    if (lane == 0) {
-      sm.red[wv][0] = r_in;
-      sm.red[wv][1] = r_out;
-      sm.red[wv][2] = r_clip;
-    }
-  } else if (lane == 0) {
-    sm.red[wv][0] = sm.red[wv][1] = sm.red[wv][2] = 0.0;
+  const double r_clip = wave_sum(led_clip);
+  double r_in = 0.0, r_out = 0.0;
+  if (EDGE) {
+    r_in = wave_sum(led_in);
+    r_out = wave_sum(led_out);
+  }
+  if (lane == 0) {
+    sm.red[wv][0] = r_in;
+    sm.red[wv][1] = r_out;
+    sm.red[wv][2] = r_clip;
   }
   if (STAGE == 2) {
     const double r_dt = wave_min(my_dtc);
@@ -966,11 +988,11 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   __syncthreads();
   if (tid == 0) {
     double a = 0, bsum = 0, c = 0, m = __longlong_as_double((long long)INF_BITS);
-    for (int w = 0; w < NT / 64; ++w) {
-      a += sm.red[w][0];
-      bsum += sm.red[w][1];
-      c += sm.red[w][2];
-      if (STAGE == 2) m = sm.red[w][3] < m ? sm.red[w][3] : m;
+    for (int k = 0; k < NT / 64; ++k) {
+      a += sm.red[k][0];
+      bsum += sm.red[k][1];
+      c += sm.red[k][2];
+      if (STAGE == 2) m = sm.red[k][3] < m ? sm.red[k][3] : m;
     }
     if (a != 0.0 || bsum != 0.0 || c != 0.0) {
       double* led = p.ledger + 4 * (long long)tile;
@@ -1040,7 +1062,7 @@ __device__ __forceinline__ void stage_tile(const Params<R> p, const int tile) {
 
 // one context: one block per tile, blocks of an XCD on a contiguous band of tiles
 template <typename R, typename S, int STAGE>
-__global__ __launch_bounds__(Geo<S>::NT, S::MINB) void stage_kernel(Params<R> p) {
+__global__ __launch_bounds__(Geo<S>::NT, STAGE == 1 ? S::B1 : S::B2) void stage_kernel(Params<R> p) {
   const int b = blockIdx.x;
   const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
   if (tile >= p.n_tiles) return;
@@ -1063,7 +1085,7 @@ struct BatchTable {
 };
 
 template <typename R, typename S, int STAGE>
-__global__ __launch_bounds__(Geo<S>::NT, S::MINB) void stage_kernel_batch(
+__global__ __launch_bounds__(Geo<S>::NT, STAGE == 1 ? S::B1 : S::B2) void stage_kernel_batch(
     const BatchTable<R>* __restrict__ tab, int phase) {
   const int b = blockIdx.x;
   const int g = (b % NXCD) * tab->per_xcd + b / NXCD;
