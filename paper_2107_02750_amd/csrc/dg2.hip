@@ -177,6 +177,7 @@ Params<R> params(const dg2_ctx* c) {
   const Layout& L = c->L;
   p.uin = reinterpret_cast<const R*>(c->ws + (c->parity ? L.u1 : L.u0));
   p.vbuf = reinterpret_cast<R*>(c->ws + (c->parity ? L.u0 : L.u1));
+  p.uout = p.vbuf;
   p.ui = reinterpret_cast<R*>(c->ws + L.ui);
   p.zv = reinterpret_cast<const R*>(c->ws + L.zv);
   p.datum = c->datum ? reinterpret_cast<const R*>(c->ws + L.datum) : nullptr;
@@ -429,7 +430,7 @@ int init_device(dg2_ctx* c, const double* zv, const double* man, int mode, const
       if (e != hipSuccess) { rc = fail(c, DG2_E_DEVICE, "staging copy: %s", hipGetErrorString(e)); break; }
     }
     Params<R> p = params<R>(c);
-    p.vbuf = reinterpret_cast<R*>(c->ws + c->L.u0);
+    p.vbuf = p.uout = reinterpret_cast<R*>(c->ws + c->L.u0);
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL((dg2k::init_kernel<R>), dim3(blocks), dim3(256), 0, c->stream, p, st, mode, eta);
     hipError_t e = hipGetLastError();
@@ -1167,12 +1168,11 @@ struct dg2_tape {
   int n_steps, K, n_ckpt, ng;
   std::vector<double> dts, t;  // t[k]: time at the start of step k
   double* ckpt;                // n_ckpt states (9n each)
-  double* seg;                 // K states
-  double* V;                   // stage-1 V^n and U^int of the step being reversed
-  double* Ui;
+  double* seg;                 // K states U^n of the segment being reversed
+  double* segV;                // and for each of its steps V^n (friction applied)
+  double* segI;                // and U^int
   double* lam;                 // cotangent of the current state
-  double* nu1;
-  double* nu2;
+  double* nu2;                 // cotangent of U^int
   double* gman;                // dJ/dn per cell
   double* gq;                  // dJ/dQ(t) per (step, stage, boundary face slot)
   double* gh;                  // gauge depths (n_steps + 1) x ng
@@ -1217,16 +1217,20 @@ struct TapeStage {
   }
 };
 
-// parameters of a recomputed step k from state U into the tape's buffers
-Params<double> tape_params(dg2_tape* tp, const double* U, int k) {
+// parameters of the recomputed step k of the current segment (its r-th step): from
+// seg[r] into segV[r], segI[r] and seg[r + 1]; the parity alternates along the segment,
+// so the stage kernels carry the time from step to step
+Params<double> tape_params(dg2_tape* tp, int r, int k) {
   dg2_ctx* c = tp->c;
+  const size_t m9 = 9 * c->n;
   Params<double> p = params<double>(c);
-  p.uin = U;
-  p.vbuf = tp->V;
-  p.ui = tp->Ui;
+  p.uin = tp->seg + r * m9;
+  p.vbuf = tp->segV + r * m9;
+  p.ui = tp->segI + r * m9;
+  p.uout = r + 1 < tp->K ? tp->seg + (r + 1) * m9 : nullptr;
   p.ctrl = tp->ctrl;
   p.ledger = tp->ledger;
-  p.parity = 0;
+  p.parity = r & 1;
   p.dt_fix = tp->dts[k];
   p.dt_max = 0.0;
   p.t_end = INFINITY;
@@ -1240,13 +1244,11 @@ int tape_set_time(dg2_tape* tp, int k) {
   return DG2_OK;
 }
 
-// recompute step k from U: V^n -> tp->V, U^int -> tp->Ui; with both stages, U^{n+1} in tp->V
-int tape_step(dg2_tape* tp, const double* U, int k, bool both) {
-  int rc = tape_set_time(tp, k);
-  if (rc) return rc;
-  Params<double> p = tape_params(tp, U, k);
-  if ((rc = with_shape<double, TapeStage>(tp->c->L.shape, tp, p, 1))) return rc;
-  if (both) rc = with_shape<double, TapeStage>(tp->c->L.shape, tp, p, 2);
+// recompute the r-th step (step k) of the current segment; U^{n+1} too if both
+int tape_step(dg2_tape* tp, int r, int k, bool both) {
+  Params<double> p = tape_params(tp, r, k);
+  int rc = with_shape<double, TapeStage>(tp->c->L.shape, tp, p, 1);
+  if (rc == DG2_OK && both) rc = with_shape<double, TapeStage>(tp->c->L.shape, tp, p, 2);
   return rc;
 }
 
@@ -1289,8 +1291,9 @@ int dg2_tape_create(dg2_ctx* c, int32_t n_steps, const double* dts, const int32_
   const size_t st = 9 * c->n * sizeof(double);
   const size_t nfs = 2 * ((size_t)c->cfg.nx + c->cfg.ny);  // boundary face slots
   hipError_t e = hipMalloc((void**)&tp->ckpt, st * tp->n_ckpt);
-  if (e == hipSuccess) e = hipMalloc((void**)&tp->seg, st * tp->K);
-  for (double** b : {&tp->V, &tp->Ui, &tp->lam, &tp->nu1, &tp->nu2})
+  for (double** b : {&tp->seg, &tp->segV, &tp->segI})
+    if (e == hipSuccess) e = hipMalloc((void**)b, st * tp->K);
+  for (double** b : {&tp->lam, &tp->nu2})
     if (e == hipSuccess) e = hipMalloc((void**)b, st);
   if (e == hipSuccess) e = hipMalloc((void**)&tp->gman, c->n * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->gq, (size_t)n_steps * 2 * nfs * sizeof(double));
@@ -1356,7 +1359,7 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
   const size_t st = 9 * c->n * sizeof(double);
   const int nseg = (int)c->knot_count.size();
   const size_t nfs = 2 * ((size_t)c->cfg.nx + c->cfg.ny);
-  const unsigned eb = (unsigned)((m9 + 255) / 256), cb = (unsigned)((n + 255) / 256);
+  const unsigned cb = (unsigned)((n + 255) / 256);
   const unsigned gb = (unsigned)((tp->ng + 63) / 64);
   // reset
   {
@@ -1379,30 +1382,22 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
   int rc = DG2_OK;
   for (int sgi = tp->n_ckpt - 1; sgi >= 0 && rc == DG2_OK; --sgi) {
     const int s0 = sgi * tp->K, s1 = std::min(tp->n_steps, s0 + tp->K);
-    // recompute the segment's states from its checkpoint
+    // recompute the segment from its checkpoint, keeping each step's V^n and U^int
     THIPC(tp, hipMemcpyAsync(tp->seg, tp->ckpt + (size_t)sgi * m9, st, hipMemcpyDeviceToDevice, sm));
-    for (int k = s0; k < s1 - 1 && rc == DG2_OK; ++k) {
-      rc = tape_step(tp, tp->seg + (size_t)(k - s0) * m9, k, true);
-      if (rc == DG2_OK)
-        THIPC(tp, hipMemcpyAsync(tp->seg + (size_t)(k - s0 + 1) * m9, tp->V, st, hipMemcpyDeviceToDevice, sm));
-    }
+    if ((rc = tape_set_time(tp, s0))) break;
+    for (int k = s0; k < s1 && rc == DG2_OK; ++k) rc = tape_step(tp, k - s0, k, k + 1 < s1);
     for (int k = s1 - 1; k >= s0 && rc == DG2_OK; --k) {
-      const double* U = tp->seg + (size_t)(k - s0) * m9;
+      const size_t r = (size_t)(k - s0) * m9;
       const double dt = tp->dts[k];
-      if ((rc = tape_step(tp, U, k, false))) break;  // V^n, U^int
       Params<double> p = params<double>(c);
-      dg2k::AdjArgs a2{tp->Ui, tp->lam, 0.5 * dt, tp->t[k] + dt, tp->nu2,
-                       tp->gq + ((size_t)k * 2 + 1) * nfs, tp->regime};
+      // stage 2: nu2 = lam / 2 + (dL/dV)(U^int)^T (dt lam / 2)
+      dg2k::AdjArgs a2{tp->segI + r, tp->lam, 0.5 * dt, tp->t[k] + dt, tp->lam, 0.5, nullptr,
+                       nullptr, 0.0, nullptr, tp->nu2, tp->gq + ((size_t)k * 2 + 1) * nfs, tp->regime};
       hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(256), 0, sm, p, a2);
-      hipLaunchKernelGGL(dg2k::adj_combine_kernel, dim3(eb), dim3(256), 0, sm, m9, tp->lam, tp->nu2,
-                         (const double*)nullptr, 0.5);
-      dg2k::AdjArgs a1{tp->V, tp->nu2, dt, tp->t[k], tp->nu1,
-                       tp->gq + ((size_t)k * 2) * nfs, tp->regime};
+      // stage 1 and friction: lam <- (dF/dU)^T (lam / 2 + nu2 + (dL/dV)(V^n)^T (dt nu2))
+      dg2k::AdjArgs a1{tp->segV + r, tp->nu2, dt, tp->t[k], tp->lam, 0.5, tp->nu2,
+                       tp->seg + r, dt, tp->gman, tp->lam, tp->gq + ((size_t)k * 2) * nfs, tp->regime};
       hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(256), 0, sm, p, a1);
-      hipLaunchKernelGGL(dg2k::adj_combine_kernel, dim3(eb), dim3(256), 0, sm, m9, tp->lam, tp->nu1,
-                         (const double*)tp->nu2, 0.5);
-      hipLaunchKernelGGL(dg2k::adj_friction_kernel, dim3(cb), dim3(256), 0, sm, p, U, tp->nu1, dt, tp->lam,
-                         tp->gman);
       if (tp->ng > 0)
         hipLaunchKernelGGL(dg2k::gauge_seed_kernel, dim3(gb), dim3(64), 0, sm, tp->lam, tp->gidx, tp->ng,
                            tp->dj + (size_t)k * tp->ng);
@@ -1466,7 +1461,7 @@ const char* dg2_tape_last_error(const dg2_tape* tp) { return tp ? tp->err.c_str(
 void dg2_tape_destroy(dg2_tape* tp) {
   if (!tp) return;
   (void)hipStreamSynchronize(tp->c->stream);
-  for (void* b : {(void*)tp->ckpt, (void*)tp->seg, (void*)tp->V, (void*)tp->Ui, (void*)tp->lam, (void*)tp->nu1,
+  for (void* b : {(void*)tp->ckpt, (void*)tp->seg, (void*)tp->segV, (void*)tp->segI, (void*)tp->lam,
                   (void*)tp->nu2, (void*)tp->gman, (void*)tp->gq, (void*)tp->gh, (void*)tp->dj, (void*)tp->gidx,
                   (void*)tp->regime, (void*)tp->ctrl, (void*)tp->ledger, (void*)tp->d_t})
     if (b) (void)hipFree(b);

@@ -126,7 +126,7 @@ __device__ __forceinline__ Dual<N> dsqrtd(Dual<N> x) {
   const double s = fsqrt(x.v);
   Dual<N> o;
   o.v = s;
-  const double h = s > 0.0 ? 0.5 / s : 0.0;
+  const double h = s > 0.0 ? 0.5 * frcp(s) : 0.0;
 #pragma unroll
   for (int k = 0; k < N; ++k) o.d[k] = h * x.d[k];
   return o;
@@ -137,7 +137,7 @@ __device__ __forceinline__ Dual<N> drsq(Dual<N> x) {
   const double y = frsq(x.v);
   Dual<N> o;
   o.v = y;
-  const double f = -0.5 * y / x.v;
+  const double f = -0.5 * y * y * y;  // -x^(-3/2) / 2
 #pragma unroll
   for (int k = 0; k < N; ++k) o.d[k] = f * x.d[k];
   return o;
@@ -148,7 +148,7 @@ __device__ __forceinline__ Dual<N> dinvcbrt(Dual<N> x) {
   const double y = finvcbrt(x.v);
   Dual<N> o;
   o.v = y;
-  const double f = -y / (3.0 * x.v);
+  const double f = -0.33333333333333333333 * (y * y) * (y * y);  // -x^(-4/3) / 3
 #pragma unroll
   for (int k = 0; k < N; ++k) o.d[k] = f * x.d[k];
   return o;
@@ -189,6 +189,22 @@ __device__ __forceinline__ DSide<N> drevise(Dual<N> h, Dual<N> qx, Dual<N> qy, d
   s.u = qx * r;
   s.v = qy * r;
   if (fabs(s.u.v) > ucap || fabs(s.v.v) > vcap_) *bad |= 2;
+  return s;
+}
+
+// the same revision of a side that carries no derivatives (a neighbour's), in plain
+// arithmetic
+template <int N>
+__device__ __forceinline__ DSide<N> drevise_const(double h, double qx, double qy, double zb, double zs,
+                                                  double ht, int* bad) {
+  const double eta = h + zb;
+  if (!(h > ht)) *bad |= 1;
+  const double r = frcp(h);
+  DSide<N> s;
+  s.h = dconst<N>(fmax0(eta - zs));
+  s.z = dconst<N>(fminr(eta, zs));
+  s.u = dconst<N>(qx * r);
+  s.v = dconst<N>(qy * r);
   return s;
 }
 
@@ -260,17 +276,80 @@ __device__ __forceinline__ void dfriction(Dual<N> gn2dt, double ht, Dual<N> h, D
 }
 
 // ---------------------------------------------------------------------------------
-// adjoint of L: nu = (dL/dV)(V)^T (alpha lam), and dJ/dQ of each inflow segment
+// adjoint of the friction step at one cell: lam (the cotangent of F) becomes the
+// cotangent of U, lam_U = (dF/dU)^T lam_F; returns dJ/dn of the cell
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double adj_friction_cell(const Params<double>& p, const double* __restrict__ U,
+                                                    long long c, double dt, double lam[9]) {
+  const long long n = p.n;
+  const double nm = p.manning ? p.manning[c] : p.n_scalar;
+  if (!(nm > 0.0)) return 0.0;
+  double u[9], lf[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    u[q] = U[q * n + c];
+    lf[q] = lam[q];
+  }
+  const double ht = p.h_tol;
+  const Dual<4> nn = dvar<4>(nm, 3);
+  const Dual<4> gn2dt = (p.g * dt) * (nn * nn);
+  double gn = 0.0;
+  // points: 0 centre; 1, 2: x +/-; 3, 4: y +/-
+#pragma unroll 1
+  for (int pt = 0; pt < 5; ++pt) {
+    const int d = pt == 0 ? 0 : (pt <= 2 ? 1 : 2);
+    const double sg = pt == 0 ? 0.0 : ((pt == 1 || pt == 3) ? 1.0 : -1.0);
+    const bool xd = d == 1, yd = d == 2;
+    const double h1 = xd ? u[1] : (yd ? u[2] : 0.0);
+    const double qx1 = xd ? u[4] : (yd ? u[5] : 0.0);
+    const double qy1 = xd ? u[7] : (yd ? u[8] : 0.0);
+    const Dual<4> h = dvar<4>(u[0] + sg * h1, 0);
+    const Dual<4> qx = dvar<4>(u[3] + sg * qx1, 1);
+    const Dual<4> qy = dvar<4>(u[6] + sg * qy1, 2);
+    Dual<4> dqx, dqy;
+    dfriction<4>(gn2dt, ht, h, qx, qy, dqx, dqy);
+    // cotangents of the increments: the centre feeds the means, a Gauss pair feeds
+    // half the difference into the slopes of its direction
+    const double cx = pt == 0 ? lf[3] : 0.5 * sg * (xd ? lf[4] : lf[5]);
+    const double cy = pt == 0 ? lf[6] : 0.5 * sg * (xd ? lf[7] : lf[8]);
+    double gin[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gin[k] = cx * dqx.d[k] + cy * dqy.d[k];
+    // the point's inputs are U0 + sg U1d
+    lam[0] += gin[0];
+    lam[3] += gin[1];
+    lam[6] += gin[2];
+    lam[1] += xd ? sg * gin[0] : 0.0;
+    lam[4] += xd ? sg * gin[1] : 0.0;
+    lam[7] += xd ? sg * gin[2] : 0.0;
+    lam[2] += yd ? sg * gin[0] : 0.0;
+    lam[5] += yd ? sg * gin[1] : 0.0;
+    lam[8] += yd ? sg * gin[2] : 0.0;
+    gn += gin[3];
+  }
+  return gn;
+}
+
+// ---------------------------------------------------------------------------------
+// adjoint of one stage: out = cl lam_c + (dL/dV)(V)^T (alpha lam) + extra, and dJ/dQ of
+// each inflow boundary face; with U_fr the friction adjoint then maps out to the
+// cotangent of U (and adds dJ/dn to gman)
 // ---------------------------------------------------------------------------------
 struct AdjArgs {
-  const double* V;     // stage input, 9 planes
-  const double* lam;   // cotangent of the stage output; mu = alpha * lam
+  const double* V;      // stage input, 9 planes
+  const double* lam;    // cotangent of the stage output; mu = alpha * lam
   double alpha;
-  double t;            // stage time (inflow discharge)
-  double* nu;          // out: 9 planes
-  double* gqf;         // out: dJ/dQ of each inflow boundary face (slots as the face
-                       // codes: W[ny], E[ny], S[nx], N[nx]), summed per segment later
-  int* regime;         // out: |= violation bits
+  double t;             // stage time (inflow discharge)
+  const double* lam_c;  // combined into the output: cl * lam_c (own cell)
+  double cl;
+  const double* extra;  // added to the output (own cell), or nullptr
+  const double* U_fr;   // friction adjoint of the step from state U_fr, or nullptr
+  double dt_fr;
+  double* gman;         // dJ/dn per cell (accumulated) with U_fr
+  double* out;          // 9 planes; may be lam_c itself (each cell reads its own first)
+  double* gqf;          // out: dJ/dQ of each inflow boundary face (slots as the face
+                        // codes: W[ny], E[ny], S[nx], N[nx]), summed per segment later
+  int* regime;          // out: |= violation bits
 };
 
 __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArgs a) {
@@ -288,30 +367,32 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
   auto zvv = [&](int iv, int jv) { return p.zv[(long long)jv * (nx + 1) + iv]; };
   auto umean = [&](long long k, bool xv) {
     const double h0 = V(k, 0);
-    return h0 > ht ? V(k, xv ? 3 : 6) / h0 : 0.0;
+    return h0 > ht ? V(k, xv ? 3 : 6) * frcp(h0) : 0.0;
   };
   int bad = 0;
   if (!(V(c, 0) > ht)) bad |= 1;
-
-  // the four faces: 0 W, 1 E, 2 S, 3 N; sgn = side of the cell's limit (+ for E/N)
-  // g_face[f][0..2]: d(face terms)/d(own face limit h, qx, qy); gQ from the ghost
-  double gface[4][3];
+  double nu[9];
 #pragma unroll
+  for (int q = 0; q < 9; ++q) nu[q] = 0.0;
+
+  // the four faces: 0 W, 1 E, 2 S, 3 N; sgn = side of the cell's limit (+ for E/N);
+  // the gradient of each face's terms with respect to the cell's own face limit
+  // (h, qx, qy) chains to the coefficients as d/dU0 = 1, d/dU1 = sgn sqrt(3)
+#pragma unroll 1
   for (int f = 0; f < 4; ++f) {
     const bool xdir = f < 2;
-    const double sgn = (f == 1 || f == 3) ? 1.0 : -1.0;
-    const int d = xdir ? 1 : 2;
+    const bool high = (f & 1) != 0;
+    const double sgn = high ? 1.0 : -1.0;
     // own face limit as Dual<4> (h, qx, qy, Q)
-    const Dual<4> h = dvar<4>(V(c, 0) + sgn * s3 * V(c, d), 0);
-    const Dual<4> qx = dvar<4>(V(c, 3) + sgn * s3 * V(c, 3 + d), 1);
-    const Dual<4> qy = dvar<4>(V(c, 6) + sgn * s3 * V(c, 6 + d), 2);
+    const double c0 = V(c, 0), c3 = V(c, 3), c6 = V(c, 6);
+    const double c1 = xdir ? V(c, 1) : V(c, 2), c4 = xdir ? V(c, 4) : V(c, 5), c7 = xdir ? V(c, 7) : V(c, 8);
+    const Dual<4> h = dvar<4>(c0 + sgn * s3 * c1, 0);
+    const Dual<4> qx = dvar<4>(c3 + sgn * s3 * c4, 1);
+    const Dual<4> qy = dvar<4>(c6 + sgn * s3 * c7, 2);
     // face bed (vertex mean) and the neighbour across the face
-    int ni = i, nj = j;
-    double zf;
-    if (f == 0) { ni = i - 1; zf = 0.5 * (zvv(i, j + 1) + zvv(i, j)); }
-    else if (f == 1) { ni = i + 1; zf = 0.5 * (zvv(i + 1, j + 1) + zvv(i + 1, j)); }
-    else if (f == 2) { nj = j - 1; zf = 0.5 * (zvv(i, j) + zvv(i + 1, j)); }
-    else { nj = j + 1; zf = 0.5 * (zvv(i, j + 1) + zvv(i + 1, j + 1)); }
+    const int ni = xdir ? (high ? i + 1 : i - 1) : i, nj = xdir ? j : (high ? j + 1 : j - 1);
+    const int va = xdir ? (high ? i + 1 : i) : i, vb = xdir ? j : (high ? j + 1 : j);  // first vertex
+    const double zf = 0.5 * (zvv(va, vb) + (xdir ? zvv(va, vb + 1) : zvv(va + 1, vb)));
     const bool inside = ni >= 0 && ni < nx && nj >= 0 && nj < ny;
     const long long nk = inside ? (long long)nj * nx + ni : c;
     // the velocity cap bound of each component (a boundary side copies the cell)
@@ -323,32 +404,32 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     DSide<4> nb;
     if (inside) {
       const double ns = -sgn;  // the neighbour's limit on its opposite side
-      const Dual<4> nh = dconst<4>(V(nk, 0) + ns * s3 * V(nk, d));
-      const Dual<4> nqx = dconst<4>(V(nk, 3) + ns * s3 * V(nk, 3 + d));
-      const Dual<4> nqy = dconst<4>(V(nk, 6) + ns * s3 * V(nk, 6 + d));
+      const double n1 = xdir ? V(nk, 1) : V(nk, 2), n4 = xdir ? V(nk, 4) : V(nk, 5);
+      const double n7 = xdir ? V(nk, 7) : V(nk, 8);
       int nbad = 0;
-      nb = drevise<4>(nh, nqx, nqy, zf, zf, ht, ucap, vcap_, &nbad);
+      nb = drevise_const<4>(V(nk, 0) + ns * s3 * n1, V(nk, 3) + ns * s3 * n4, V(nk, 6) + ns * s3 * n7, zf,
+                            zf, ht, &nbad);
       bad |= nbad & 1;
       if (!(nb.h.v > 0.0)) bad |= 1;
     } else {
       // ghost beyond a boundary face, from the own side in the normal frame
-      const int code = xdir ? p.bface[(f == 0 ? 0 : ny) + j] : p.bface[2 * ny + (f == 2 ? 0 : nx) + i];
+      const int code = xdir ? p.bface[(high ? ny : 0) + j] : p.bface[2 * ny + (high ? nx : 0) + i];
       const int kind = code & 255;
-      const double inward = (f == 0 || f == 2) ? 1.0 : -1.0;
+      const double inward = high ? -1.0 : 1.0;
       Dual<4> un = xdir ? own.u : own.v, ut = xdir ? own.v : own.u;
       Dual<4> gh = own.h, gun = un, gut = ut;
       if (kind == 1) {
         gun = -un;
       } else if (kind == 2) {
-        const Seg& s = p.segs[(code >> 8) - 1];
-        gh = dconst<4>(s.h_b);
-        gun = dconst<4>(xdir ? s.u_b : s.v_b);
-        gut = dconst<4>(xdir ? s.v_b : s.u_b);
+        const Seg& sg = p.segs[(code >> 8) - 1];
+        gh = dconst<4>(sg.h_b);
+        gun = dconst<4>(xdir ? sg.u_b : sg.v_b);
+        gut = dconst<4>(xdir ? sg.v_b : sg.u_b);
       } else if (kind == 3) {
-        const Seg& s = p.segs[(code >> 8) - 1];
-        qslot = xdir ? (f == 0 ? 0 : ny) + j : 2 * ny + (f == 2 ? 0 : nx) + i;
-        const Dual<4> Q = dvar<4>(hydrograph(s, p.knots, p.knots + p.max_knots, a.t), 3);
-        const Dual<4> qn = Q * (1.0 / s.width);
+        const Seg& sg = p.segs[(code >> 8) - 1];
+        qslot = xdir ? (high ? ny : 0) + j : 2 * ny + (high ? nx : 0) + i;
+        const Dual<4> Q = dvar<4>(hydrograph(sg, p.knots, p.knots + p.max_knots, a.t), 3);
+        const Dual<4> qn = Q * (1.0 / sg.width);
         const Dual<4> hc = dcbrtd(qn * qn * (1.0 / g));
         const Dual<4> hg = own.h.v > hc.v ? own.h : hc;
         gh = hg;
@@ -362,29 +443,32 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     }
     // flux through the face: left state = the W/S cell's side
     Dual<4> F[3];
-    const bool own_left = (f == 1 || f == 3);
-    if (own_left) dhll<4>(g, own, nb, xdir, F);
+    if (high) dhll<4>(g, own, nb, xdir, F);
     else dhll<4>(g, nb, own, xdir, F);
     // stored order [mass, x-mom, y-mom]: on y faces the HLL gives [mass, y-mom, x-mom]
     const Dual<4> Fs[3] = {F[0], xdir ? F[1] : F[2], xdir ? F[2] : F[1]};
-    // cotangent of each stored flux component, from both cells sharing the face
+    // cotangent of each stored flux component, from both cells sharing the face:
     // L0 gets -(F_high - F_low)/dx, L1 (this direction) gets cc (F_high + F_low)
-    const int k1 = xdir ? 1 : 2;
     double mt[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const double own0 = mu(c, 3 * m), own1 = mu(c, 3 * m + k1);
+      const double own0 = mu(c, 3 * m), own1 = xdir ? mu(c, 3 * m + 1) : mu(c, 3 * m + 2);
       // this face is the cell's high face (E/N): -idx; low face (W/S): +idx
-      double v = (own_left ? -idx : idx) * own0 + cc * own1;
+      double v = (high ? -idx : idx) * own0 + cc * own1;
       if (inside) {
-        const double nb0 = mu(nk, 3 * m), nb1 = mu(nk, 3 * m + k1);
-        v += (own_left ? idx : -idx) * nb0 + cc * nb1;
+        const double nb0 = mu(nk, 3 * m), nb1 = xdir ? mu(nk, 3 * m + 1) : mu(nk, 3 * m + 2);
+        v += (high ? idx : -idx) * nb0 + cc * nb1;
       }
       mt[m] = v;
     }
-    Dual<4> J = mt[0] * Fs[0] + mt[1] * Fs[1] + mt[2] * Fs[2];
+    const Dual<4> J = mt[0] * Fs[0] + mt[1] * Fs[1] + mt[2] * Fs[2];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gface[f][k] = J.d[k];
+    for (int k = 0; k < 3; ++k) {
+      const double gk = J.d[k];
+      nu[3 * k] += gk;
+      nu[3 * k + 1] += xdir ? sgn * s3 * gk : 0.0;
+      nu[3 * k + 2] += xdir ? 0.0 : sgn * s3 * gk;
+    }
     if (qslot >= 0) a.gqf[qslot] = J.d[3];
   }
 
@@ -424,90 +508,26 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     // local part of mu . L: -cc * gs in L1 of this direction; -s0 in the momentum mean
     // of this direction's normal component, -s1 in its slope
     const int qn0 = xdir ? 3 : 6, qn1 = xdir ? 4 : 8;
-    Dual<6> J = (-cc * mu(c, 1 * 0 + d)) * gs[0] + (-cc * mu(c, 3 + d)) * gs[1] + (-cc * mu(c, 6 + d)) * gs[2];
+    Dual<6> J = (-cc * mu(c, d)) * gs[0] + (-cc * mu(c, 3 + d)) * gs[1] + (-cc * mu(c, 6 + d)) * gs[2];
     J = J - mu(c, qn0) * s0 - mu(c, qn1) * s1;
-    const int fH = xdir ? 1 : 3, fL = xdir ? 0 : 2;
+    // high-side limit: d/dU0 = 1, d/dU1d = sqrt(3); low side: 1, -sqrt(3)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      gface[fH][k] += J.d[k];
-      gface[fL][k] += J.d[3 + k];
+      nu[3 * k] += J.d[k] + J.d[3 + k];
+      nu[3 * k + d] += s3 * (J.d[k] - J.d[3 + k]);
     }
   }
 
-  // chain the face-limit gradients to the nine coefficients
-  double nu[9];
+  // the combination with the incoming cotangents, then the friction adjoint
 #pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    nu[3 * v] = gface[0][v] + gface[1][v] + gface[2][v] + gface[3][v];
-    nu[3 * v + 1] = s3 * (gface[1][v] - gface[0][v]);
-    nu[3 * v + 2] = s3 * (gface[3][v] - gface[2][v]);
+  for (int q = 0; q < 9; ++q) nu[q] += a.cl * a.lam_c[q * n + c] + (a.extra ? a.extra[q * n + c] : 0.0);
+  if (a.U_fr) {
+    const double gn = adj_friction_cell(p, a.U_fr, c, a.dt_fr, nu);
+    if (a.gman) a.gman[c] += gn;
   }
 #pragma unroll
-  for (int q = 0; q < 9; ++q) a.nu[q * n + c] = nu[q];
+  for (int q = 0; q < 9; ++q) a.out[q * n + c] = nu[q];
   if (bad) atomicOr(a.regime, bad);
-}
-
-// ---------------------------------------------------------------------------------
-// adjoint of the friction step: lam_U = (dF/dU)^T lam_F, dJ/dn per cell
-// ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void adj_friction_kernel(Params<double> p, const double* __restrict__ U,
-                                                           const double* __restrict__ lamF, double dt,
-                                                           double* __restrict__ lamU, double* __restrict__ gman) {
-  const long long n = p.n;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  double lu[9], lf[9], u[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    lf[q] = lamF[q * n + c];
-    lu[q] = lf[q];
-    u[q] = U[q * n + c];
-  }
-  const double nm = p.manning ? p.manning[c] : p.n_scalar;
-  if (nm > 0.0) {
-    const double ht = p.h_tol;
-    const Dual<4> nn = dvar<4>(nm, 3);
-    const Dual<4> gn2dt = (p.g * dt) * (nn * nn);
-    double gn = 0.0;
-    // points: 0 centre; 1, 2: x +/-; 3, 4: y +/-
-#pragma unroll
-    for (int pt = 0; pt < 5; ++pt) {
-      const int d = pt == 0 ? 0 : (pt <= 2 ? 1 : 2);
-      const double sg = pt == 0 ? 0.0 : ((pt == 1 || pt == 3) ? 1.0 : -1.0);
-      const Dual<4> h = dvar<4>(u[0] + sg * (d ? u[d] : 0.0), 0);
-      const Dual<4> qx = dvar<4>(u[3] + sg * (d ? u[3 + d] : 0.0), 1);
-      const Dual<4> qy = dvar<4>(u[6] + sg * (d ? u[6 + d] : 0.0), 2);
-      Dual<4> dqx, dqy;
-      dfriction<4>(gn2dt, ht, h, qx, qy, dqx, dqy);
-      // cotangents of the increments: the centre feeds the means, a Gauss pair feeds
-      // half the difference into the slopes of its direction
-      const double cx = pt == 0 ? lf[3] : 0.5 * sg * lf[3 + d];
-      const double cy = pt == 0 ? lf[6] : 0.5 * sg * lf[6 + d];
-      double gin[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) gin[k] = cx * dqx.d[k] + cy * dqy.d[k];
-      // the point's inputs are U0 + sg U1d
-      lu[0] += gin[0];
-      lu[3] += gin[1];
-      lu[6] += gin[2];
-      if (d) {
-        lu[d] += sg * gin[0];
-        lu[3 + d] += sg * gin[1];
-        lu[6 + d] += sg * gin[2];
-      }
-      gn += gin[3];
-    }
-    if (gman) gman[c] += gn;
-  }
-#pragma unroll
-  for (int q = 0; q < 9; ++q) lamU[q * n + c] = lu[q];
-}
-
-// lam_int = lam / 2 + nu2 (in place into nu2); lam_F = lam / 2 + lam_int + nu1
-__global__ void adj_combine_kernel(long long m, const double* __restrict__ lam, double* __restrict__ a,
-                                   const double* __restrict__ b, double cl) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < m) a[k] = cl * lam[k] + a[k] + (b ? b[k] : 0.0);
 }
 
 // a recomputation's control block takes the time of step k (one thread)

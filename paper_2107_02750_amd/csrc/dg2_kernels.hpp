@@ -91,7 +91,9 @@ __device__ __forceinline__ void cand_clear(Cand& c) {
 template <typename R>
 struct Params {
   const R* __restrict__ uin;   // U^n (the stage-1 input; stage 2 reads ui)
-  R* __restrict__ vbuf;        // V^n out (stage 1); V^n in, U^{n+1} out (stage 2)
+  R* vbuf;                     // V^n out (stage 1); V^n in (stage 2)
+  R* uout;                     // U^{n+1} out (stage 2): vbuf itself in a plain run, so
+                               // neither pointer is restrict
   R* __restrict__ ui;          // U^int out (stage 1)
   const R* __restrict__ zv;    // vertex bed (relative to the owner tile's datum if datum)
   const R* __restrict__ datum; // per tile, whole metres (FP32 with a bed datum), or nullptr
@@ -962,7 +964,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
       for (int q = 0; q < 9; ++q) (p.ui + q * n)[ck] = u[q];
     } else {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) (p.vbuf + q * n)[ck] = u[q];
+      for (int q = 0; q < 9; ++q) (p.uout + q * n)[ck] = u[q];
       my_dtc = cell_dtc(p, u[0], u[1], u[2], u[3], u[6]);
     }
   }
