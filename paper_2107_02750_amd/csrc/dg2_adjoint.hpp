@@ -13,11 +13,10 @@
 // (dL/dV)^T mu is gathered per cell: L of a cell depends on its own coefficients
 // through its four face sides (Gauss fluxes, bed source, and the four face fluxes)
 // and on a neighbour's only through the shared face flux. So each cell needs the
-// cotangent of each of its face fluxes (collected from the cell and the neighbour)
-// and the derivative of those fluxes and of its own local terms with respect to its
-// own face limits. Those local derivatives come from forward-mode dual numbers run
-// through the same face, flux and friction formulas as the forward kernels; the
-// products with the cotangents and the chain to the nine coefficients are written out.
+// cotangent of each of its face fluxes (collected from the cell and the neighbour),
+// which it takes back through the same face, flux and friction formulas as the
+// forward kernels (reverse mode written out per formula, recomputing the forward
+// values) to its own face limits, and from there to its nine coefficients.
 //
 // The regime is checked while the adjoint runs: a cell at or below h_tol, a face
 // depth not above zero, or an active face-velocity cap set a flag (the derivative
@@ -26,253 +25,154 @@
 
 namespace dg2k {
 
-// value and N first derivatives
-template <int N>
-struct Dual {
-  double v;
-  double d[N];
+// ---------------------------------------------------------------------------------
+// reverse-mode pieces: each takes the inputs of a forward formula and the cotangents
+// of its outputs, recomputes what it needs, and returns the cotangents of the inputs
+// ---------------------------------------------------------------------------------
+
+// a face side in the normal frame: depth, normal and tangential velocity
+struct NSide {
+  double h, un, ut;
 };
 
-template <int N>
-__device__ __forceinline__ Dual<N> dconst(double v) {
-  Dual<N> r;
-  r.v = v;
+// HLL (the forward kernel's hll, same branches): cotangents fb of [mass, normal
+// momentum, tangential momentum] -> cotangents of the two sides
+__device__ __forceinline__ void hll_rev(double g, NSide L, NSide R, const double fb[3], NSide& Lb,
+                                        NSide& Rb) {
+  Lb = NSide{0.0, 0.0, 0.0};
+  Rb = NSide{0.0, 0.0, 0.0};
+  const bool wL = L.h > 0.0, wR = R.h > 0.0;
+  if (!wL && !wR) return;  // both dry: zero flux
+  const double cL = fsqrt(g * L.h), cR = fsqrt(g * R.h);
+  const double us = 0.5 * (L.un + R.un) + cL - cR;
+  const double cs = 0.5 * (cL + cR) + 0.25 * (L.un - R.un);
+  const double a1 = L.un - cL, a2 = us - cs, b1 = R.un + cR, b2 = us + cs;
+  const double sL = wL ? (wR ? (a1 <= a2 ? a1 : a2) : L.un - cL) : R.un - 2.0 * cR;
+  const double sR = wL ? (wR ? (b1 >= b2 ? b1 : b2) : L.un + 2.0 * cL) : R.un + cR;
+  const double qL = L.h * L.un, qR = R.h * R.un;
+  const double FL[3] = {qL, qL * L.un + 0.5 * g * L.h * L.h, qL * L.ut};
+  const double FR[3] = {qR, qR * R.un + 0.5 * g * R.h * R.h, qR * R.ut};
+  const double UL[3] = {L.h, qL, L.h * L.ut};
+  const double UR[3] = {R.h, qR, R.h * R.ut};
+  double FLb[3] = {0.0, 0.0, 0.0}, FRb[3] = {0.0, 0.0, 0.0}, ULb[3] = {0.0, 0.0, 0.0},
+         URb[3] = {0.0, 0.0, 0.0};
+  double sLb = 0.0, sRb = 0.0;
+  if (sL >= 0.0) {
 #pragma unroll
-  for (int k = 0; k < N; ++k) r.d[k] = 0.0;
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> dvar(double v, int k) {
-  Dual<N> r = dconst<N>(v);
-  r.d[k] = 1.0;
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator+(Dual<N> a, Dual<N> b) {
-  Dual<N> r;
-  r.v = a.v + b.v;
+    for (int m = 0; m < 3; ++m) FLb[m] = fb[m];
+  } else if (sR <= 0.0) {
 #pragma unroll
-  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator-(Dual<N> a, Dual<N> b) {
-  Dual<N> r;
-  r.v = a.v - b.v;
+    for (int m = 0; m < 3; ++m) FRb[m] = fb[m];
+  } else {
+    // mid = (sR FL - sL FR + sL sR (UR - UL)) / (sR - sL)
+    const double inv = frcp(sR - sL), ss = sL * sR;
+    double invb = 0.0, ssb = 0.0;
 #pragma unroll
-  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator-(Dual<N> a) {
-  Dual<N> r;
-  r.v = -a.v;
-#pragma unroll
-  for (int k = 0; k < N; ++k) r.d[k] = -a.d[k];
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator*(Dual<N> a, Dual<N> b) {
-  Dual<N> r;
-  r.v = a.v * b.v;
-#pragma unroll
-  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator*(double a, Dual<N> b) {
-  Dual<N> r;
-  r.v = a * b.v;
-#pragma unroll
-  for (int k = 0; k < N; ++k) r.d[k] = a * b.d[k];
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator*(Dual<N> b, double a) { return a * b; }
-template <int N>
-__device__ __forceinline__ Dual<N> operator+(Dual<N> a, double b) {
-  a.v += b;
-  return a;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator+(double b, Dual<N> a) {
-  a.v += b;
-  return a;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator-(Dual<N> a, double b) {
-  a.v -= b;
-  return a;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator-(double b, Dual<N> a) {
-  return dconst<N>(b) - a;
-}
-// 1/x: d(1/x) = -dx / x^2
-template <int N>
-__device__ __forceinline__ Dual<N> drcp(Dual<N> x) {
-  const double r = frcp(x.v);
-  Dual<N> o;
-  o.v = r;
-#pragma unroll
-  for (int k = 0; k < N; ++k) o.d[k] = -r * r * x.d[k];
-  return o;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator/(Dual<N> a, Dual<N> b) { return a * drcp(b); }
-// sqrt(x) for x > 0 (0 with zero derivative otherwise)
-template <int N>
-__device__ __forceinline__ Dual<N> dsqrtd(Dual<N> x) {
-  const double s = fsqrt(x.v);
-  Dual<N> o;
-  o.v = s;
-  const double h = s > 0.0 ? 0.5 * frcp(s) : 0.0;
-#pragma unroll
-  for (int k = 0; k < N; ++k) o.d[k] = h * x.d[k];
-  return o;
-}
-// x^(-1/2) for x > 0
-template <int N>
-__device__ __forceinline__ Dual<N> drsq(Dual<N> x) {
-  const double y = frsq(x.v);
-  Dual<N> o;
-  o.v = y;
-  const double f = -0.5 * y * y * y;  // -x^(-3/2) / 2
-#pragma unroll
-  for (int k = 0; k < N; ++k) o.d[k] = f * x.d[k];
-  return o;
-}
-// x^(-1/3) for x > 0
-template <int N>
-__device__ __forceinline__ Dual<N> dinvcbrt(Dual<N> x) {
-  const double y = finvcbrt(x.v);
-  Dual<N> o;
-  o.v = y;
-  const double f = -0.33333333333333333333 * (y * y) * (y * y);  // -x^(-4/3) / 3
-#pragma unroll
-  for (int k = 0; k < N; ++k) o.d[k] = f * x.d[k];
-  return o;
-}
-// x^(1/3) for x >= 0
-template <int N>
-__device__ __forceinline__ Dual<N> dcbrtd(Dual<N> x) {
-  const double y = cbrt(x.v);
-  Dual<N> o;
-  o.v = y;
-  const double f = y > 0.0 ? y / (3.0 * x.v) : 0.0;
-#pragma unroll
-  for (int k = 0; k < N; ++k) o.d[k] = f * x.d[k];
-  return o;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> dsel(bool c, Dual<N> a, Dual<N> b) { return c ? a : b; }
-template <int N>
-__device__ __forceinline__ Dual<N> dmax(Dual<N> a, Dual<N> b) { return a.v >= b.v ? a : b; }
-template <int N>
-__device__ __forceinline__ Dual<N> dmin(Dual<N> a, Dual<N> b) { return a.v <= b.v ? a : b; }
-
-// a face side after the revision, as in the forward kernel (FP64 eta form); *capped
-// is set when the velocity cap bounds a component (outside the regime)
-template <int N>
-struct DSide {
-  Dual<N> h, u, v, z;
-};
-template <int N>
-__device__ __forceinline__ DSide<N> drevise(Dual<N> h, Dual<N> qx, Dual<N> qy, double zb, double zs,
-                                            double ht, double ucap, double vcap_, int* bad) {
-  DSide<N> s;
-  const Dual<N> eta = h + zb;
-  s.h = dmax(eta - zs, dconst<N>(0.0));
-  s.z = dmin(eta, dconst<N>(zs));
-  if (!(h.v > ht)) *bad |= 1;
-  const Dual<N> r = drcp(h);
-  s.u = qx * r;
-  s.v = qy * r;
-  if (fabs(s.u.v) > ucap || fabs(s.v.v) > vcap_) *bad |= 2;
-  return s;
-}
-
-// the same revision of a side that carries no derivatives (a neighbour's), in plain
-// arithmetic
-template <int N>
-__device__ __forceinline__ DSide<N> drevise_const(double h, double qx, double qy, double zb, double zs,
-                                                  double ht, int* bad) {
-  const double eta = h + zb;
-  if (!(h > ht)) *bad |= 1;
-  const double r = frcp(h);
-  DSide<N> s;
-  s.h = dconst<N>(fmax0(eta - zs));
-  s.z = dconst<N>(fminr(eta, zs));
-  s.u = dconst<N>(qx * r);
-  s.v = dconst<N>(qy * r);
-  return s;
-}
-
-// HLL in the normal frame, wet-wet or a dry side, as in the forward kernel
-template <int N>
-__device__ __forceinline__ void dhll(double g, DSide<N> L, DSide<N> R, bool xdir, Dual<N> f[3]) {
-  // normal / tangential velocities of each side
-  const Dual<N> unL = xdir ? L.u : L.v, utL = xdir ? L.v : L.u;
-  const Dual<N> unR = xdir ? R.u : R.v, utR = xdir ? R.v : R.u;
-  const Dual<N> hL = L.h, hR = R.h;
-  const bool wL = hL.v > 0.0, wR = hR.v > 0.0;
-  const Dual<N> cL = dsqrtd(g * hL), cR = dsqrtd(g * hR);
-  const Dual<N> us = 0.5 * (unL + unR) + cL - cR;
-  const Dual<N> cs = 0.5 * (cL + cR) + 0.25 * (unL - unR);
-  const Dual<N> sLw = dmin(unL - cL, us - cs), sRw = dmax(unR + cR, us + cs);
-  const Dual<N> sL = wL ? (wR ? sLw : unL - cL) : unR - 2.0 * cR;
-  const Dual<N> sR = wL ? (wR ? sRw : unL + 2.0 * cL) : unR + cR;
-  const Dual<N> qL = hL * unL, qR = hR * unR;
-  const Dual<N> FL[3] = {qL, qL * unL + 0.5 * g * hL * hL, qL * utL};
-  const Dual<N> FR[3] = {qR, qR * unR + 0.5 * g * hR * hR, qR * utR};
-  const Dual<N> UL[3] = {hL, qL, hL * utL};
-  const Dual<N> UR[3] = {hR, qR, hR * utR};
-  const Dual<N> inv = drcp(sR - sL), ss = sL * sR;
-  const bool up = sL.v >= 0.0, dn = sR.v <= 0.0, dry = !wL && !wR;
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    const Dual<N> mid = (sR * FL[m] - sL * FR[m] + ss * (UR[m] - UL[m])) * inv;
-    f[m] = dry ? dconst<N>(0.0) : (up ? FL[m] : (dn ? FR[m] : mid));
+    for (int m = 0; m < 3; ++m) {
+      const double tm = sR * FL[m] - sL * FR[m] + ss * (UR[m] - UL[m]);
+      invb += fb[m] * tm;
+      const double tb = fb[m] * inv;
+      sRb += tb * FL[m];
+      FLb[m] = tb * sR;
+      sLb -= tb * FR[m];
+      FRb[m] = -tb * sL;
+      ssb += tb * (UR[m] - UL[m]);
+      URb[m] = tb * ss;
+      ULb[m] = -tb * ss;
+    }
+    sLb += ssb * sR + invb * inv * inv;
+    sRb += ssb * sL - invb * inv * inv;
+  }
+  // wave speeds
+  double cLb = 0.0, cRb = 0.0, usb = 0.0, csb = 0.0;
+  if (wL && wR) {
+    if (a1 <= a2) { Lb.un += sLb; cLb -= sLb; } else { usb += sLb; csb -= sLb; }
+    if (b1 >= b2) { Rb.un += sRb; cRb += sRb; } else { usb += sRb; csb += sRb; }
+  } else if (wL) {
+    Lb.un += sLb + sRb;
+    cLb += 2.0 * sRb - sLb;
+  } else {
+    Rb.un += sLb + sRb;
+    cRb += sRb - 2.0 * sLb;
+  }
+  Lb.un += 0.5 * usb + 0.25 * csb;
+  Rb.un += 0.5 * usb - 0.25 * csb;
+  cLb += usb + 0.5 * csb;
+  cRb += 0.5 * csb - usb;
+  // fluxes and states of each side: F = [q, q un + g h^2 / 2, q ut], U = [h, q, h ut]
+  {
+    const double qb = FLb[0] + FLb[1] * L.un + FLb[2] * L.ut + ULb[1];
+    Lb.un += FLb[1] * qL + qb * L.h;
+    Lb.ut += FLb[2] * qL + ULb[2] * L.h;
+    Lb.h += FLb[1] * g * L.h + ULb[0] + ULb[2] * L.ut + qb * L.un;
+    if (cL > 0.0) Lb.h += cLb * 0.5 * g * frcp(cL);
+  }
+  {
+    const double qb = FRb[0] + FRb[1] * R.un + FRb[2] * R.ut + URb[1];
+    Rb.un += FRb[1] * qR + qb * R.h;
+    Rb.ut += FRb[2] * qR + URb[2] * R.h;
+    Rb.h += FRb[1] * g * R.h + URb[0] + URb[2] * R.ut + qb * R.un;
+    if (cR > 0.0) Rb.h += cRb * 0.5 * g * frcp(cR);
   }
 }
 
-// physical flux along a normal at a Gauss point (velocities zero at or below h_tol)
-template <int N>
-__device__ __forceinline__ void dgauss(double g, double ht, Dual<N> h, Dual<N> qn, Dual<N> qt, Dual<N> f[3]) {
-  const bool wet = h.v > ht;
-  const Dual<N> r = drcp(dmax(h, dconst<N>(Tiny<double>::v)));
-  const Dual<N> un = wet ? qn * r : dconst<N>(0.0), ut = wet ? qt * r : dconst<N>(0.0);
-  const Dual<N> q = h * un;
-  f[0] = q;
-  f[1] = q * un + 0.5 * g * h * h;
-  f[2] = q * ut;
+// physical flux at a Gauss point (gauss_flux): cotangents fb -> (h, qn, qt)
+__device__ __forceinline__ void gauss_rev(double g, double ht, double h, double qn, double qt, const double fb[3],
+                                          double& hb, double& qnb, double& qtb) {
+  const bool wet = h > ht;
+  const double r = frcp(fmaxr(h, Tiny<double>::v));
+  const double un = wet ? qn * r : 0.0, ut = wet ? qt * r : 0.0;
+  const double q = h * un;
+  // f0 = q, f1 = q un + g h^2 / 2, f2 = q ut
+  const double qb = fb[0] + fb[1] * un + fb[2] * ut;
+  const double unb = fb[1] * q + qb * h, utb = fb[2] * q;
+  hb = fb[1] * g * h + qb * un;
+  qnb = wet ? unb * r : 0.0;
+  qtb = wet ? utb * r : 0.0;
+  hb -= wet ? (unb * un + utb * ut) * r : 0.0;  // d(q/h)/dh = -(q/h)/h
 }
 
-// the split-implicit friction increment at one point, as friction_inc
-template <int N>
-__device__ __forceinline__ void dfriction(Dual<N> gn2dt, double ht, Dual<N> h, Dual<N> qx, Dual<N> qy,
-                                          Dual<N>& dqx, Dual<N>& dqy) {
-  const bool wet = h.v > ht;
-  if (!wet) {
-    dqx = dqy = dconst<N>(0.0);
-    return;
-  }
-  const Dual<N> y = dinvcbrt(h);
-  const Dual<N> y3 = y * y * y;
-  const Dual<N> u = qx * y3, v = qy * y3;
-  const Dual<N> s2 = u * u + v * v;
-  if (!(s2.v > 0.0)) {
-    dqx = dqy = dconst<N>(0.0);
-    return;
-  }
-  const Dual<N> rs = drsq(s2);
-  const Dual<N> w = gn2dt * (y3 * y);
-  const Dual<N> a = w * u * u * rs, b = w * v * v * rs;
-  const Dual<N> ab = a + b;
-  const Dual<N> d1 = 1.0 + 2.0 * a + b, d2 = 1.0 + a + 2.0 * b;
-  const Dual<N> inv = drcp(d1 * d2);
-  dqx = -(qx * ab * d2 * inv);
-  dqy = -(qy * ab * d1 * inv);
+// the split-implicit friction increment at one point (friction_inc): cotangents
+// (cx, cy) of (dqx, dqy) -> (h, qx, qy) and gn2dt
+__device__ __forceinline__ void friction_rev(double gn2dt, double ht, double h, double qx, double qy, double cx,
+                                             double cy, double& hb, double& qxb, double& qyb, double& gb) {
+  hb = qxb = qyb = gb = 0.0;
+  if (!(h > ht)) return;
+  const double y = finvcbrt(h);  // h^(-1/3)
+  const double y3 = y * y * y;   // 1/h
+  const double u = qx * y3, v = qy * y3;
+  const double s2 = u * u + v * v;
+  if (!(s2 > 0.0)) return;
+  const double rs = frsq(s2);    // 1/|u|
+  const double y4 = y3 * y;
+  const double w = gn2dt * y4;
+  const double a = w * u * u * rs, b = w * v * v * rs;
+  const double ab = a + b;
+  const double d1 = 1.0 + 2.0 * a + b, d2 = 1.0 + a + 2.0 * b;
+  const double inv = frcp(d1 * d2);
+  const double P = ab * inv;
+  // dqx = -qx d2 P, dqy = -qy d1 P
+  qxb = -cx * d2 * P;
+  qyb = -cy * d1 * P;
+  double d2b = -cx * qx * P, d1b = -cy * qy * P;
+  const double Pb = -cx * qx * d2 - cy * qy * d1;
+  const double abb = Pb * inv, invb = Pb * ab;
+  const double Db = -invb * inv * inv;  // inv = 1 / (d1 d2)
+  d1b += Db * d2;
+  d2b += Db * d1;
+  const double ab_ = abb + 2.0 * d1b + d2b, bb_ = abb + d1b + 2.0 * d2b;  // of a, b
+  const double wb = (ab_ * u * u + bb_ * v * v) * rs;
+  double ub = 2.0 * ab_ * w * u * rs, vb = 2.0 * bb_ * w * v * rs;
+  const double rsb = ab_ * w * u * u + bb_ * w * v * v;
+  const double s2b = -0.5 * rsb * rs * rs * rs;  // rs = s2^(-1/2)
+  ub += 2.0 * u * s2b;
+  vb += 2.0 * v * s2b;
+  gb = wb * y4;
+  qxb += ub * y3;
+  qyb += vb * y3;
+  const double y3b = ub * qx + vb * qy;
+  const double yb = wb * gn2dt * 4.0 * y3 + y3b * 3.0 * y * y;  // w = gn2dt y^4, y3 = y^3
+  hb = -0.33333333333333333333 * yb * y4;                         // dy/dh = -y^4 / 3
 }
 
 // ---------------------------------------------------------------------------------
@@ -291,9 +191,8 @@ __device__ __forceinline__ double adj_friction_cell(const Params<double>& p, con
     lf[q] = lam[q];
   }
   const double ht = p.h_tol;
-  const Dual<4> nn = dvar<4>(nm, 3);
-  const Dual<4> gn2dt = (p.g * dt) * (nn * nn);
-  double gn = 0.0;
+  const double gdt = p.g * dt, gn2dt = gdt * (nm * nm);
+  double gsum = 0.0;
   // points: 0 centre; 1, 2: x +/-; 3, 4: y +/-
 #pragma unroll 1
   for (int pt = 0; pt < 5; ++pt) {
@@ -303,31 +202,25 @@ __device__ __forceinline__ double adj_friction_cell(const Params<double>& p, con
     const double h1 = xd ? u[1] : (yd ? u[2] : 0.0);
     const double qx1 = xd ? u[4] : (yd ? u[5] : 0.0);
     const double qy1 = xd ? u[7] : (yd ? u[8] : 0.0);
-    const Dual<4> h = dvar<4>(u[0] + sg * h1, 0);
-    const Dual<4> qx = dvar<4>(u[3] + sg * qx1, 1);
-    const Dual<4> qy = dvar<4>(u[6] + sg * qy1, 2);
-    Dual<4> dqx, dqy;
-    dfriction<4>(gn2dt, ht, h, qx, qy, dqx, dqy);
     // cotangents of the increments: the centre feeds the means, a Gauss pair feeds
     // half the difference into the slopes of its direction
     const double cx = pt == 0 ? lf[3] : 0.5 * sg * (xd ? lf[4] : lf[5]);
     const double cy = pt == 0 ? lf[6] : 0.5 * sg * (xd ? lf[7] : lf[8]);
-    double gin[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) gin[k] = cx * dqx.d[k] + cy * dqy.d[k];
+    double hb, qxb, qyb, gb;
+    friction_rev(gn2dt, ht, u[0] + sg * h1, u[3] + sg * qx1, u[6] + sg * qy1, cx, cy, hb, qxb, qyb, gb);
     // the point's inputs are U0 + sg U1d
-    lam[0] += gin[0];
-    lam[3] += gin[1];
-    lam[6] += gin[2];
-    lam[1] += xd ? sg * gin[0] : 0.0;
-    lam[4] += xd ? sg * gin[1] : 0.0;
-    lam[7] += xd ? sg * gin[2] : 0.0;
-    lam[2] += yd ? sg * gin[0] : 0.0;
-    lam[5] += yd ? sg * gin[1] : 0.0;
-    lam[8] += yd ? sg * gin[2] : 0.0;
-    gn += gin[3];
+    lam[0] += hb;
+    lam[3] += qxb;
+    lam[6] += qyb;
+    lam[1] += xd ? sg * hb : 0.0;
+    lam[4] += xd ? sg * qxb : 0.0;
+    lam[7] += xd ? sg * qyb : 0.0;
+    lam[2] += yd ? sg * hb : 0.0;
+    lam[5] += yd ? sg * qxb : 0.0;
+    lam[8] += yd ? sg * qyb : 0.0;
+    gsum += gb;
   }
-  return gn;
+  return gsum * 2.0 * gdt * nm;  // gn2dt = g dt n^2
 }
 
 // ---------------------------------------------------------------------------------
@@ -375,85 +268,71 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
 #pragma unroll
   for (int q = 0; q < 9; ++q) nu[q] = 0.0;
 
-  // the four faces: 0 W, 1 E, 2 S, 3 N; sgn = side of the cell's limit (+ for E/N);
-  // the gradient of each face's terms with respect to the cell's own face limit
-  // (h, qx, qy) chains to the coefficients as d/dU0 = 1, d/dU1 = sgn sqrt(3)
+  // the four faces: 0 W, 1 E, 2 S, 3 N; sgn = side of the cell's limit (+ for E/N).
+  // The cotangent of a face's flux (from both cells sharing it) goes back through the
+  // HLL flux, the ghost state (boundary faces) and the revision to the cell's own face
+  // limit (h, qx, qy), which chains to the coefficients as d/dU0 = 1, d/dU1 = sgn sqrt(3)
 #pragma unroll 1
   for (int f = 0; f < 4; ++f) {
     const bool xdir = f < 2;
     const bool high = (f & 1) != 0;
     const double sgn = high ? 1.0 : -1.0;
-    // own face limit as Dual<4> (h, qx, qy, Q)
     const double c0 = V(c, 0), c3 = V(c, 3), c6 = V(c, 6);
     const double c1 = xdir ? V(c, 1) : V(c, 2), c4 = xdir ? V(c, 4) : V(c, 5), c7 = xdir ? V(c, 7) : V(c, 8);
-    const Dual<4> h = dvar<4>(c0 + sgn * s3 * c1, 0);
-    const Dual<4> qx = dvar<4>(c3 + sgn * s3 * c4, 1);
-    const Dual<4> qy = dvar<4>(c6 + sgn * s3 * c7, 2);
+    const double ho = c0 + sgn * s3 * c1, qxo = c3 + sgn * s3 * c4, qyo = c6 + sgn * s3 * c7;
     // face bed (vertex mean) and the neighbour across the face
     const int ni = xdir ? (high ? i + 1 : i - 1) : i, nj = xdir ? j : (high ? j + 1 : j - 1);
     const int va = xdir ? (high ? i + 1 : i) : i, vb = xdir ? j : (high ? j + 1 : j);  // first vertex
     const double zf = 0.5 * (zvv(va, vb) + (xdir ? zvv(va, vb + 1) : zvv(va + 1, vb)));
     const bool inside = ni >= 0 && ni < nx && nj >= 0 && nj < ny;
     const long long nk = inside ? (long long)nj * nx + ni : c;
-    // the velocity cap bound of each component (a boundary side copies the cell)
+    // own side after the revision (both sides share the face bed in this regime)
+    const double ro = frcp(ho);
+    const double hs = fmax0((ho + zf) - zf), uo = qxo * ro, vo = qyo * ro;
+    if (!(ho > ht) || !(hs > 0.0)) bad |= 1;
     const double ucap = fmax(fabs(umean(c, true)), fabs(umean(nk, true))) + slack;
     const double vcap_ = fmax(fabs(umean(c, false)), fabs(umean(nk, false))) + slack;
-    const DSide<4> own = drevise<4>(h, qx, qy, zf, zf, ht, ucap, vcap_, &bad);
-    int qslot = -1;  // face slot of an inflow face
-    if (!(own.h.v > 0.0)) bad |= 1;
-    DSide<4> nb;
+    if (fabs(uo) > ucap || fabs(vo) > vcap_) bad |= 2;
+    const NSide own{hs, xdir ? uo : vo, xdir ? vo : uo};
+    NSide nb;
+    int kind = -1, qslot = -1;
+    double qn = 0.0, hc = 0.0, inward = 0.0, width = 1.0;
     if (inside) {
       const double ns = -sgn;  // the neighbour's limit on its opposite side
       const double n1 = xdir ? V(nk, 1) : V(nk, 2), n4 = xdir ? V(nk, 4) : V(nk, 5);
       const double n7 = xdir ? V(nk, 7) : V(nk, 8);
-      int nbad = 0;
-      nb = drevise_const<4>(V(nk, 0) + ns * s3 * n1, V(nk, 3) + ns * s3 * n4, V(nk, 6) + ns * s3 * n7, zf,
-                            zf, ht, &nbad);
-      bad |= nbad & 1;
-      if (!(nb.h.v > 0.0)) bad |= 1;
+      const double hn = V(nk, 0) + ns * s3 * n1, qxn = V(nk, 3) + ns * s3 * n4, qyn = V(nk, 6) + ns * s3 * n7;
+      const double rn = frcp(hn);
+      const double hsn = fmax0((hn + zf) - zf);
+      if (!(hn > ht) || !(hsn > 0.0)) bad |= 1;
+      nb = NSide{hsn, xdir ? qxn * rn : qyn * rn, xdir ? qyn * rn : qxn * rn};
     } else {
       // ghost beyond a boundary face, from the own side in the normal frame
       const int code = xdir ? p.bface[(high ? ny : 0) + j] : p.bface[2 * ny + (high ? nx : 0) + i];
-      const int kind = code & 255;
-      const double inward = high ? -1.0 : 1.0;
-      Dual<4> un = xdir ? own.u : own.v, ut = xdir ? own.v : own.u;
-      Dual<4> gh = own.h, gun = un, gut = ut;
+      kind = code & 255;
+      inward = high ? -1.0 : 1.0;
+      nb = own;
       if (kind == 1) {
-        gun = -un;
+        nb.un = -own.un;
       } else if (kind == 2) {
         const Seg& sg = p.segs[(code >> 8) - 1];
-        gh = dconst<4>(sg.h_b);
-        gun = dconst<4>(xdir ? sg.u_b : sg.v_b);
-        gut = dconst<4>(xdir ? sg.v_b : sg.u_b);
+        nb = NSide{sg.h_b, xdir ? sg.u_b : sg.v_b, xdir ? sg.v_b : sg.u_b};
       } else if (kind == 3) {
         const Seg& sg = p.segs[(code >> 8) - 1];
         qslot = xdir ? (high ? ny : 0) + j : 2 * ny + (high ? nx : 0) + i;
-        const Dual<4> Q = dvar<4>(hydrograph(sg, p.knots, p.knots + p.max_knots, a.t), 3);
-        const Dual<4> qn = Q * (1.0 / sg.width);
-        const Dual<4> hc = dcbrtd(qn * qn * (1.0 / g));
-        const Dual<4> hg = own.h.v > hc.v ? own.h : hc;
-        gh = hg;
-        gun = hg.v > 0.0 ? inward * (qn / hg) : dconst<4>(0.0);
-        gut = dconst<4>(0.0);
+        width = sg.width;
+        qn = hydrograph(sg, p.knots, p.knots + p.max_knots, a.t) / width;
+        hc = dcbrt(qn * qn / g);
+        const double hg = own.h > hc ? own.h : hc;
+        nb = NSide{hg, hg > 0.0 ? inward * (qn / hg) : 0.0, 0.0};
       }
-      nb.h = gh;
-      nb.u = xdir ? gun : gut;
-      nb.v = xdir ? gut : gun;
-      nb.z = dconst<4>(zf);
     }
-    // flux through the face: left state = the W/S cell's side
-    Dual<4> F[3];
-    if (high) dhll<4>(g, own, nb, xdir, F);
-    else dhll<4>(g, nb, own, xdir, F);
-    // stored order [mass, x-mom, y-mom]: on y faces the HLL gives [mass, y-mom, x-mom]
-    const Dual<4> Fs[3] = {F[0], xdir ? F[1] : F[2], xdir ? F[2] : F[1]};
-    // cotangent of each stored flux component, from both cells sharing the face:
+    // cotangent of each stored flux component [mass, x-mom, y-mom], from both cells:
     // L0 gets -(F_high - F_low)/dx, L1 (this direction) gets cc (F_high + F_low)
     double mt[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       const double own0 = mu(c, 3 * m), own1 = xdir ? mu(c, 3 * m + 1) : mu(c, 3 * m + 2);
-      // this face is the cell's high face (E/N): -idx; low face (W/S): +idx
       double v = (high ? -idx : idx) * own0 + cc * own1;
       if (inside) {
         const double nb0 = mu(nk, 3 * m), nb1 = xdir ? mu(nk, 3 * m + 1) : mu(nk, 3 * m + 2);
@@ -461,61 +340,97 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
       }
       mt[m] = v;
     }
-    const Dual<4> J = mt[0] * Fs[0] + mt[1] * Fs[1] + mt[2] * Fs[2];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double gk = J.d[k];
-      nu[3 * k] += gk;
-      nu[3 * k + 1] += xdir ? sgn * s3 * gk : 0.0;
-      nu[3 * k + 2] += xdir ? 0.0 : sgn * s3 * gk;
+    // in the normal frame: [mass, normal momentum, tangential momentum]
+    const double fb[3] = {mt[0], xdir ? mt[1] : mt[2], xdir ? mt[2] : mt[1]};
+    NSide Lb, Rb;
+    if (high) hll_rev(g, own, nb, fb, Lb, Rb);
+    else hll_rev(g, nb, own, fb, Lb, Rb);
+    NSide ob = high ? Lb : Rb;          // the own side's cotangent
+    const NSide gb = high ? Rb : Lb;    // the other side's (a ghost's depends on the own side)
+    if (kind == 0) {                    // transmissive: a copy
+      ob.h += gb.h; ob.un += gb.un; ob.ut += gb.ut;
+    } else if (kind == 1) {             // wall: the normal velocity reversed
+      ob.h += gb.h; ob.un -= gb.un; ob.ut += gb.ut;
+    } else if (kind == 3) {             // critical-depth inflow: depends on h and Q
+      const double hg = own.h > hc ? own.h : hc;
+      double hgb = gb.h, qnb = 0.0;
+      if (hg > 0.0) {
+        const double r = frcp(hg);
+        qnb += gb.un * inward * r;
+        hgb -= gb.un * inward * qn * r * r;
+      }
+      if (own.h > hc) ob.h += hgb;
+      else if (hc > 0.0 && qn != 0.0) qnb += hgb * 2.0 * hc / (3.0 * qn);  // hc = (qn^2 / g)^(1/3)
+      a.gqf[qslot] = qnb / width;
     }
-    if (qslot >= 0) a.gqf[qslot] = J.d[3];
+    // back through the revision: u = qx / h, v = qy / h, h* = h
+    const double ub = xdir ? ob.un : ob.ut, vbk = xdir ? ob.ut : ob.un;
+    const double hb = ob.h - (ub * uo + vbk * vo) * ro, qxb = ub * ro, qyb = vbk * ro;
+    nu[0] += hb;
+    nu[3] += qxb;
+    nu[6] += qyb;
+    nu[1] += xdir ? sgn * s3 * hb : 0.0;
+    nu[4] += xdir ? sgn * s3 * qxb : 0.0;
+    nu[7] += xdir ? sgn * s3 * qyb : 0.0;
+    nu[2] += xdir ? 0.0 : sgn * s3 * hb;
+    nu[5] += xdir ? 0.0 : sgn * s3 * qxb;
+    nu[8] += xdir ? 0.0 : sgn * s3 * qyb;
   }
 
-  // local terms of the cell's own L (Gauss fluxes and bed source), per direction
-#pragma unroll
+  // local terms of the cell's own L (Gauss fluxes and bed source), per direction:
+  // mu . L_local = -cc (mu_d gs0 + mu_{3+d} gs1 + mu_{6+d} gs2) - mu_qn0 s0 - mu_qn1 s1
+#pragma unroll 1
   for (int dir = 0; dir < 2; ++dir) {
     const bool xdir = dir == 0;
-    const int d = xdir ? 1 : 2;
-    // Dual<6>: the high-side limit (E/N: h, qx, qy) then the low-side limit (W/S)
-    Dual<6> hH = dvar<6>(V(c, 0) + s3 * V(c, d), 0), qxH = dvar<6>(V(c, 3) + s3 * V(c, 3 + d), 1),
-            qyH = dvar<6>(V(c, 6) + s3 * V(c, 6 + d), 2);
-    Dual<6> hL = dvar<6>(V(c, 0) - s3 * V(c, d), 3), qxL = dvar<6>(V(c, 3) - s3 * V(c, 3 + d), 4),
-            qyL = dvar<6>(V(c, 6) - s3 * V(c, 6 + d), 5);
+    const double c0 = V(c, 0), c3 = V(c, 3), c6 = V(c, 6);
+    const double c1 = xdir ? V(c, 1) : V(c, 2), c4 = xdir ? V(c, 4) : V(c, 5), c7 = xdir ? V(c, 7) : V(c, 8);
+    const double hH = c0 + s3 * c1, qxH = c3 + s3 * c4, qyH = c6 + s3 * c7;
+    const double hL = c0 - s3 * c1, qxL = c3 - s3 * c4, qyL = c6 - s3 * c7;
     double zH, zL;
     if (xdir) { zH = 0.5 * (zvv(i + 1, j + 1) + zvv(i + 1, j)); zL = 0.5 * (zvv(i, j + 1) + zvv(i, j)); }
     else { zH = 0.5 * (zvv(i, j + 1) + zvv(i + 1, j + 1)); zL = 0.5 * (zvv(i, j) + zvv(i + 1, j)); }
-    int dummy = 0;
-    const DSide<6> sH = drevise<6>(hH, qxH, qyH, zH, zH, ht, 1e300, 1e300, &dummy);
-    const DSide<6> sL = drevise<6>(hL, qxL, qyL, zL, zL, ht, 1e300, 1e300, &dummy);
-    const Dual<6> hb0 = 0.5 * (sH.h + sL.h), hb1 = (sH.h - sL.h) * i2s3;
-    const Dual<6> qxH2 = sH.h * sH.u, qxL2 = sL.h * sL.u, qyH2 = sH.h * sH.v, qyL2 = sL.h * sL.v;
-    const Dual<6> qb0 = 0.5 * (qxH2 + qxL2), qb1 = (qxH2 - qxL2) * i2s3;
-    const Dual<6> rb0 = 0.5 * (qyH2 + qyL2), rb1 = (qyH2 - qyL2) * i2s3;
-    const Dual<6> zb1 = (sH.z - sL.z) * i2s3;
-    Dual<6> Gp[3], Gm[3];
-    if (xdir) {
-      dgauss<6>(g, ht, hb0 + hb1, qb0 + qb1, rb0 + rb1, Gp);
-      dgauss<6>(g, ht, hb0 - hb1, qb0 - qb1, rb0 - rb1, Gm);
-    } else {
-      dgauss<6>(g, ht, hb0 + hb1, rb0 + rb1, qb0 + qb1, Gp);
-      dgauss<6>(g, ht, hb0 - hb1, rb0 - rb1, qb0 - qb1, Gm);
-    }
-    // sums in stored order [mass, x-mom, y-mom]
-    const Dual<6> gs[3] = {Gp[0] + Gm[0], xdir ? Gp[1] + Gm[1] : Gp[2] + Gm[2],
-                           xdir ? Gp[2] + Gm[2] : Gp[1] + Gm[1]};
-    const Dual<6> s0 = k2s3 * hb0 * zb1, s1 = k2s3 * hb1 * zb1;
-    // local part of mu . L: -cc * gs in L1 of this direction; -s0 in the momentum mean
-    // of this direction's normal component, -s1 in its slope
-    const int qn0 = xdir ? 3 : 6, qn1 = xdir ? 4 : 8;
-    Dual<6> J = (-cc * mu(c, d)) * gs[0] + (-cc * mu(c, 3 + d)) * gs[1] + (-cc * mu(c, 6 + d)) * gs[2];
-    J = J - mu(c, qn0) * s0 - mu(c, qn1) * s1;
-    // high-side limit: d/dU0 = 1, d/dU1d = sqrt(3); low side: 1, -sqrt(3)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      nu[3 * k] += J.d[k] + J.d[3 + k];
-      nu[3 * k + d] += s3 * (J.d[k] - J.d[3 + k]);
-    }
+    // revised sides (the bed of each side is its own face bed)
+    const double rH = frcp(hH), rL = frcp(hL);
+    const double shH = fmax0((hH + zH) - zH), shL = fmax0((hL + zL) - zL);
+    const double uH = qxH * rH, vH = qyH * rH, uL = qxL * rL, vL = qyL * rL;
+    const double zb1 = (fminr(hH + zH, zH) - fminr(hL + zL, zL)) * i2s3;
+    const double hb0 = 0.5 * (shH + shL), hb1 = (shH - shL) * i2s3;
+    const double qxH2 = shH * uH, qxL2 = shL * uL, qyH2 = shH * vH, qyL2 = shL * vL;
+    const double qb0 = 0.5 * (qxH2 + qxL2), qb1 = (qxH2 - qxL2) * i2s3;
+    const double rb0 = 0.5 * (qyH2 + qyL2), rb1 = (qyH2 - qyL2) * i2s3;
+    // cotangents of the stored Gauss sums and of the source terms
+    const int d = xdir ? 1 : 2;
+    const double gsb[3] = {-cc * mu(c, d), -cc * mu(c, 3 + d), -cc * mu(c, 6 + d)};
+    const double s0b = -(xdir ? mu(c, 3) : mu(c, 6)), s1b = -(xdir ? mu(c, 4) : mu(c, 8));
+    // Gauss flux cotangents in the normal frame (y faces: normal momentum is y)
+    const double fbn[3] = {gsb[0], xdir ? gsb[1] : gsb[2], xdir ? gsb[2] : gsb[1]};
+    const double qn0 = xdir ? qb0 : rb0, qn1 = xdir ? qb1 : rb1, qt0 = xdir ? rb0 : qb0, qt1 = xdir ? rb1 : qb1;
+    double hpb, qnpb, qtpb, hmb, qnmb, qtmb;
+    gauss_rev(g, ht, hb0 + hb1, qn0 + qn1, qt0 + qt1, fbn, hpb, qnpb, qtpb);
+    gauss_rev(g, ht, hb0 - hb1, qn0 - qn1, qt0 - qt1, fbn, hmb, qnmb, qtmb);
+    // s0 = k2s3 hb0 zb1, s1 = k2s3 hb1 zb1 (zb1 does not depend on the coefficients here)
+    const double hb0b = hpb + hmb + s0b * k2s3 * zb1, hb1b = hpb - hmb + s1b * k2s3 * zb1;
+    const double qn0b = qnpb + qnmb, qn1b = qnpb - qnmb, qt0b = qtpb + qtmb, qt1b = qtpb - qtmb;
+    const double qb0b = xdir ? qn0b : qt0b, qb1b = xdir ? qn1b : qt1b;
+    const double rb0b = xdir ? qt0b : qn0b, rb1b = xdir ? qt1b : qn1b;
+    const double qxH2b = 0.5 * qb0b + i2s3 * qb1b, qxL2b = 0.5 * qb0b - i2s3 * qb1b;
+    const double qyH2b = 0.5 * rb0b + i2s3 * rb1b, qyL2b = 0.5 * rb0b - i2s3 * rb1b;
+    const double shHb = 0.5 * hb0b + i2s3 * hb1b + qxH2b * uH + qyH2b * vH;
+    const double shLb = 0.5 * hb0b - i2s3 * hb1b + qxL2b * uL + qyL2b * vL;
+    const double uHb = qxH2b * shH, vHb = qyH2b * shH, uLb = qxL2b * shL, vLb = qyL2b * shL;
+    // through the revision of each side
+    const double hHb = shHb - (uHb * uH + vHb * vH) * rH, qxHb = uHb * rH, qyHb = vHb * rH;
+    const double hLb = shLb - (uLb * uL + vLb * vL) * rL, qxLb = uLb * rL, qyLb = vLb * rL;
+    // high side: d/dU0 = 1, d/dU1d = sqrt(3); low side: 1, -sqrt(3)
+    nu[0] += hHb + hLb;
+    nu[3] += qxHb + qxLb;
+    nu[6] += qyHb + qyLb;
+    nu[1] += xdir ? s3 * (hHb - hLb) : 0.0;
+    nu[4] += xdir ? s3 * (qxHb - qxLb) : 0.0;
+    nu[7] += xdir ? s3 * (qyHb - qyLb) : 0.0;
+    nu[2] += xdir ? 0.0 : s3 * (hHb - hLb);
+    nu[5] += xdir ? 0.0 : s3 * (qxHb - qxLb);
+    nu[8] += xdir ? 0.0 : s3 * (qyHb - qyLb);
   }
 
   // the combination with the incoming cotangents, then the friction adjoint

@@ -5,9 +5,9 @@ inflow hydrograph, over a replayed time-step schedule.
 
 Checked: the recorded gauge depths (1e-12 relative), the gradients of a gauge misfit
 with respect to the per-cell Manning n (summed over zones) and the hydrograph knots
-(1e-7 relative to the largest component) and the initial state (1e-6), independence
-from the checkpoint spacing (bit for bit), the torch.autograd.Function wrapper, and
-the regime check. Measured agreement on this case: 2e-9 (zones), 3e-9 (knots),
+(1e-7 relative to the largest component) and the initial state (1e-6), also with wall
+edges and a fixed-state segment, independence from the checkpoint spacing (bit for
+bit), the torch.autograd.Function wrapper, and the regime check. Measured agreement on this case: 2e-9 (zones), 3e-9 (knots),
 2.5e-8 (initial state, largest at boundary cells); over 5 to 40 steps it does not
 grow. The gradients are sums over cells and steps with cancellation that the two
 sides form in different orders on states that differ in the last bits; the larger
@@ -113,6 +113,37 @@ def test_adjoint_matches_reference_gradient(dg2):
     assert np.array_equal(tape2.forward(), hs)
     gm2, gq2, gu2 = tape2.backward(2.0 * (hs - href), len(sc.boundaries[0].q_knots))
     assert np.array_equal(gm2, gm) and np.array_equal(gq2, gq) and np.array_equal(gu2, gu)
+
+
+def test_adjoint_with_walls_and_a_fixed_segment(dg2):
+    """Wall edges (reflected normal velocity) and a fixed-state segment (a constant
+    ghost) besides the inflow: gradients of the zone values and of the initial state
+    against the reference. The fixed state is close to the local one (2 cm deeper, the
+    local mean velocity, a small tangential one): a state far from it drives face
+    velocities past their cap next to the segment, which is outside the regime."""
+    base = case()
+    P = Oracle(base).planes()
+    h_b = float(P[0][14:18, -1].mean()) + 0.02
+    u_b = float((P[3] / P[0])[14:18, -1].mean())
+    sc = base.replace(edge_kind=(S.TRANSMISSIVE, S.TRANSMISSIVE, S.WALL, S.WALL),
+                      boundaries=base.boundaries + [S.Boundary(S.E, S.FIXED, 14, 18, h_b=h_b,
+                                                               u_b=u_b, v_b=0.01)])
+    dts = schedule(sc, 25)
+    gi = gauges(N)
+    href = href_of(sc, dts, gi)
+    _, hs_ref, gz_ref, gq_ref, gu_ref = reference(sc, dts, gi, href)
+    sim = dg2.DG2(sc, dg2.FP64)
+    tape = dg2.Tape(sim, dts, gi)
+    hs = tape.forward()
+    assert np.abs(hs - hs_ref).max() <= 1e-12 * np.abs(hs_ref).max()
+    gm, gq, gu = tape.backward(2.0 * (hs - href), len(sc.boundaries[0].q_knots))
+    zi = S.zone_index(N, 4)
+    gz = np.array([gm.reshape(-1)[zi.reshape(-1) == z].sum() for z in range(16)])
+    ez = np.abs(gz - gz_ref).max() / np.abs(gz_ref).max()
+    eq = np.abs(gq - gq_ref).max() / np.abs(gq_ref).max()
+    eu = np.abs(gu - gu_ref).max() / np.abs(gu_ref).max()
+    print(f"walls + fixed segment: zones {ez:.2e}, knots {eq:.2e}, U0 {eu:.2e}", flush=True)
+    assert ez <= 1e-7 and eq <= 1e-7 and eu <= 1e-6
 
 
 def test_autograd_function(dg2):
