@@ -262,8 +262,17 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     const double h0 = V(k, 0);
     return h0 > ht ? V(k, xv ? 3 : 6) * frcp(h0) : 0.0;
   };
+  // the cell's own coefficients, cotangents and mean velocities, read once
+  double vc[9], mc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    vc[q] = V(c, q);
+    mc[q] = mu(c, q);
+  }
+  const double u0c = vc[0] > ht ? vc[3] * frcp(vc[0]) : 0.0;
+  const double v0c = vc[0] > ht ? vc[6] * frcp(vc[0]) : 0.0;
   int bad = 0;
-  if (!(V(c, 0) > ht)) bad |= 1;
+  if (!(vc[0] > ht)) bad |= 1;
   double nu[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) nu[q] = 0.0;
@@ -277,9 +286,8 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     const bool xdir = f < 2;
     const bool high = (f & 1) != 0;
     const double sgn = high ? 1.0 : -1.0;
-    const double c0 = V(c, 0), c3 = V(c, 3), c6 = V(c, 6);
-    const double c1 = xdir ? V(c, 1) : V(c, 2), c4 = xdir ? V(c, 4) : V(c, 5), c7 = xdir ? V(c, 7) : V(c, 8);
-    const double ho = c0 + sgn * s3 * c1, qxo = c3 + sgn * s3 * c4, qyo = c6 + sgn * s3 * c7;
+    const double c1 = xdir ? vc[1] : vc[2], c4 = xdir ? vc[4] : vc[5], c7 = xdir ? vc[7] : vc[8];
+    const double ho = vc[0] + sgn * s3 * c1, qxo = vc[3] + sgn * s3 * c4, qyo = vc[6] + sgn * s3 * c7;
     // face bed (vertex mean) and the neighbour across the face
     const int ni = xdir ? (high ? i + 1 : i - 1) : i, nj = xdir ? j : (high ? j + 1 : j - 1);
     const int va = xdir ? (high ? i + 1 : i) : i, vb = xdir ? j : (high ? j + 1 : j);  // first vertex
@@ -290,8 +298,8 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     const double ro = frcp(ho);
     const double hs = fmax0((ho + zf) - zf), uo = qxo * ro, vo = qyo * ro;
     if (!(ho > ht) || !(hs > 0.0)) bad |= 1;
-    const double ucap = fmax(fabs(umean(c, true)), fabs(umean(nk, true))) + slack;
-    const double vcap_ = fmax(fabs(umean(c, false)), fabs(umean(nk, false))) + slack;
+    const double ucap = fmax(fabs(u0c), fabs(inside ? umean(nk, true) : u0c)) + slack;
+    const double vcap_ = fmax(fabs(v0c), fabs(inside ? umean(nk, false) : v0c)) + slack;
     if (fabs(uo) > ucap || fabs(vo) > vcap_) bad |= 2;
     const NSide own{hs, xdir ? uo : vo, xdir ? vo : uo};
     NSide nb;
@@ -332,7 +340,7 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     double mt[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const double own0 = mu(c, 3 * m), own1 = xdir ? mu(c, 3 * m + 1) : mu(c, 3 * m + 2);
+      const double own0 = mc[3 * m], own1 = xdir ? mc[3 * m + 1] : mc[3 * m + 2];
       double v = (high ? -idx : idx) * own0 + cc * own1;
       if (inside) {
         const double nb0 = mu(nk, 3 * m), nb1 = xdir ? mu(nk, 3 * m + 1) : mu(nk, 3 * m + 2);
@@ -382,10 +390,9 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
 #pragma unroll 1
   for (int dir = 0; dir < 2; ++dir) {
     const bool xdir = dir == 0;
-    const double c0 = V(c, 0), c3 = V(c, 3), c6 = V(c, 6);
-    const double c1 = xdir ? V(c, 1) : V(c, 2), c4 = xdir ? V(c, 4) : V(c, 5), c7 = xdir ? V(c, 7) : V(c, 8);
-    const double hH = c0 + s3 * c1, qxH = c3 + s3 * c4, qyH = c6 + s3 * c7;
-    const double hL = c0 - s3 * c1, qxL = c3 - s3 * c4, qyL = c6 - s3 * c7;
+    const double c1 = xdir ? vc[1] : vc[2], c4 = xdir ? vc[4] : vc[5], c7 = xdir ? vc[7] : vc[8];
+    const double hH = vc[0] + s3 * c1, qxH = vc[3] + s3 * c4, qyH = vc[6] + s3 * c7;
+    const double hL = vc[0] - s3 * c1, qxL = vc[3] - s3 * c4, qyL = vc[6] - s3 * c7;
     double zH, zL;
     if (xdir) { zH = 0.5 * (zvv(i + 1, j + 1) + zvv(i + 1, j)); zL = 0.5 * (zvv(i, j + 1) + zvv(i, j)); }
     else { zH = 0.5 * (zvv(i, j + 1) + zvv(i + 1, j + 1)); zL = 0.5 * (zvv(i, j) + zvv(i + 1, j)); }
@@ -399,9 +406,9 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     const double qb0 = 0.5 * (qxH2 + qxL2), qb1 = (qxH2 - qxL2) * i2s3;
     const double rb0 = 0.5 * (qyH2 + qyL2), rb1 = (qyH2 - qyL2) * i2s3;
     // cotangents of the stored Gauss sums and of the source terms
-    const int d = xdir ? 1 : 2;
-    const double gsb[3] = {-cc * mu(c, d), -cc * mu(c, 3 + d), -cc * mu(c, 6 + d)};
-    const double s0b = -(xdir ? mu(c, 3) : mu(c, 6)), s1b = -(xdir ? mu(c, 4) : mu(c, 8));
+    const double gsb[3] = {-cc * (xdir ? mc[1] : mc[2]), -cc * (xdir ? mc[4] : mc[5]),
+                           -cc * (xdir ? mc[7] : mc[8])};
+    const double s0b = -(xdir ? mc[3] : mc[6]), s1b = -(xdir ? mc[4] : mc[8]);
     // Gauss flux cotangents in the normal frame (y faces: normal momentum is y)
     const double fbn[3] = {gsb[0], xdir ? gsb[1] : gsb[2], xdir ? gsb[2] : gsb[1]};
     const double qn0 = xdir ? qb0 : rb0, qn1 = xdir ? qb1 : rb1, qt0 = xdir ? rb0 : qb0, qt1 = xdir ? rb1 : qb1;
