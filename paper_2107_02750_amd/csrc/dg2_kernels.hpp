@@ -213,11 +213,18 @@ __device__ inline double hydrograph(const Seg& s, const double* kt, const double
   return kq[k0 + k] + a * (kq[k0 + k + 1] - kq[k0 + k]);
 }
 
+// a value that is the same in every lane, kept in scalar registers
+__device__ __forceinline__ double uniform(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // the step's time step, identical in every block of both stage launches
 template <typename R>
 __device__ __forceinline__ void step_time(const Params<R>& p, double& t, double& dt, double& t_next,
                                           double& dt_cfl) {
-  t = p.ctrl->t[p.parity];
+  t = uniform(p.ctrl->t[p.parity]);
   const double m = cand_read(p.ctrl->dtc[p.parity]);
   double d = (m == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * m;
   dt_cfl = d;
@@ -432,26 +439,51 @@ __device__ inline double forcing_dtc(const Params<R>& p, double t) {
   return m;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+// Wave-wide sum / min of a double, the same value in every lane, in a fixed order:
+// an xor butterfly over the 32-lane halves by ds_swizzle (the lane pattern is an
+// immediate, so no lane-address registers are held), then the two halves combined.
+template <int XOR>
+__device__ __forceinline__ double swizzle_xor(double x) {
+  constexpr int pattern = (XOR << 10) | 0x1F;  // bit mode: and 0x1F, or 0, xor XOR
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)b, pattern);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), pattern);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+__device__ __forceinline__ double lane_value(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum(double x) {
+  x += swizzle_xor<1>(x);
+  x += swizzle_xor<2>(x);
+  x += swizzle_xor<4>(x);
+  x += swizzle_xor<8>(x);
+  x += swizzle_xor<16>(x);
+  return lane_value(x, 0) + lane_value(x, 32);
+}
+__device__ __forceinline__ double dmin2(double a, double b) { return b < a ? b : a; }
 __device__ __forceinline__ double wave_min(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double y = __shfl_xor(x, o, 64);
-    x = y < x ? y : x;
-  }
-  return x;
+  x = dmin2(x, swizzle_xor<1>(x));
+  x = dmin2(x, swizzle_xor<2>(x));
+  x = dmin2(x, swizzle_xor<4>(x));
+  x = dmin2(x, swizzle_xor<8>(x));
+  x = dmin2(x, swizzle_xor<16>(x));
+  return dmin2(lane_value(x, 0), lane_value(x, 32));
 }
 
+// every thread reads the slots itself (uniform loads): a cross-lane reduction here
+// would share its lane-address arithmetic with the reductions at the end of the stage
+// kernels, which then holds those registers through the whole kernel
 __device__ __forceinline__ double cand_read(const Cand& c) {
-  const int lane = threadIdx.x & 63;
-  const double v = lane < NSLOT ? __longlong_as_double((long long)c.s[lane * SLOT_STRIDE])
-                                : __longlong_as_double((long long)INF_BITS);
-  return wave_min(v);
+  unsigned long long m = c.s[0];
+#pragma unroll
+  for (int q = 1; q < NSLOT; ++q) {
+    const unsigned long long v = c.s[q * SLOT_STRIDE];
+    m = v < m ? v : m;  // positive doubles order like their bit patterns
+  }
+  return __longlong_as_double((long long)m);
 }
 
 // ---------------------------------------------------------------------------------
@@ -811,7 +843,10 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
     const R Lg[9] = {R(0), -c * gx[0], -c * gy[0], -sx0, -c * gx[1] - sx1, -c * gy[1],
                      -sy0, -c * gx[2], -c * gy[2] - sy1};
 #pragma unroll
-    for (int q = 0; q < 9; ++q) w[q] = va[q] + dtr * Lg[q];
+    for (int q = 0; q < 9; ++q) {
+      w[q] = va[q] + dtr * Lg[q];
+      asm volatile("" : "+v"(w[q]));  // formed here: the compiler would otherwise sink it
+    }                                 // past the flux phase, keeping its inputs live
     if (STAGE == 1 && active) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) (p.vbuf + q * n)[ck] = va[q];
