@@ -1158,9 +1158,9 @@ template <typename R, typename S>
 struct SmemFV1 {
   static constexpr int TX = S::X, TY = S::Y, NT = TX * TY;
   static constexpr int RX = TX + 2, RB = RX * (TY + 2);   // 1-cell cross halo
-  R h[RB], qx[RB], qy[RB], z0[RB];  // box means after friction; bed means
-  R f[3][RB];                       // fluxes of one direction: the west (then south)
-                                    // face of each position
+  R h[RB], u[RB], v[RB], z0[RB];  // box depths and velocities after friction; bed means
+  R f[3][RB];                     // fluxes of one direction: the west (then south)
+                                  // face of each position
   double red[NT / 64][4];
 };
 
@@ -1178,74 +1178,41 @@ __device__ __forceinline__ void fv1_side(R h, R zb, R zs, R& hs, R& zss) {
   }
 }
 
-template <typename R, typename S>
-__global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
+// One FV1 step over one tile. EDGE is false for tiles whose halo lies inside the
+// domain: no clamping, no boundary faces.
+template <typename R, typename S, bool EDGE>
+__device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, const int tile, const int i0,
+                                         const int j0, const double t, const double dt, const long long k,
+                                         const double t_next) {
   using SM = SmemFV1<R, S>;
   constexpr int TX = SM::TX, TY = SM::TY, NT = SM::NT, RX = SM::RX;
   constexpr int NRING = 2 * (TX + TY);
-  static_assert(NT % 64 == 0 && NRING <= NT && TY <= 64 && 64 + TX <= NT,
-                "tile must give whole waves and room for the halo items");
-  __shared__ SM sm;
-  const int b = blockIdx.x;
-  const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
-  if (tile >= p.n_tiles) return;
+  Ctrl* ctl = p.ctrl;
   const int tid = threadIdx.x;
   const int nx = p.nx, ny = p.ny;
   const long long n = p.n;
-  const int i0 = (tile % p.tiles_x) * TX, j0 = (tile / p.tiles_x) * TY;
   const int ci = i0 + tid % TX, cj = j0 + tid / TX;
-  const bool active = ci < nx && cj < ny;
+  const bool active = !EDGE || (ci < nx && cj < ny);
   const unsigned ck = (unsigned)(cj * nx + ci);
   const R* __restrict__ hin = p.uin;
   const R* __restrict__ qxin = p.uin + 3 * n;
   const R* __restrict__ qyin = p.uin + 6 * n;
-
-  // the step's time step from the ring slot of this step
-  Ctrl* ctl = p.ctrl;
-  const int a = p.parity, o = 1 - p.parity;
-  const long long k = ctl->step[a];
-  const double t = ctl->t[a];
-  const double mm = cand_read(ctl->dtr[k % 3]);
-  double dt = (mm == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * mm;
-  const double dt_cfl = dt;
-  if (p.dt_max > 0.0 && p.dt_max < dt) dt = p.dt_max;
-  double t_next = t + dt;
-  if (p.t_end - t <= dt) {
-    dt = p.t_end - t;
-    t_next = p.t_end;
-  }
-  if (!(dt > 0.0)) {  // past t_end: carry the state over
-    if (active) {
-      (p.vbuf)[ck] = hin[ck];
-      (p.vbuf + 3 * n)[ck] = qxin[ck];
-      (p.vbuf + 6 * n)[ck] = qyin[ck];
-    }
-    if (tile == 0 && tid == 0) {
-      ctl->t[o] = t;
-      ctl->step[o] = k;
-      ctl->dt_used[a] = 0.0;
-    }
-    return;
-  }
-  if (tile == 0 && tid == 0) {
-    ctl->t[o] = t_next;
-    ctl->step[o] = k + 1;
-    ctl->dt_used[a] = dt;
-    cand_clear(ctl->dtr[(k + 2) % 3]);
-    if (dt_cfl < 1e-12) atomicOr(&ctl->health, 2);
-  }
   const R dtr = R(dt);
   const R ht = p.h_tol, g = p.g;
   const R dT = tile_datum(p, i0, j0);
 
-  // ---- phase 1: the box means (friction applied) and bed means of the box cells ----
-  auto load = [&](int ab, int bb) {  // box position (ab, bb), clamped to the domain
+  // ---- phase 1: the box depths and velocities (friction applied) and bed means ----
+  // returns the cell's discharges after friction
+  auto load = [&](int ab, int bb, R& qx, R& qy) {  // box position (ab, bb)
     int i = i0 - 1 + ab, j = j0 - 1 + bb;
-    i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
-    j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
+    if (EDGE) {
+      i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+      j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
+    }
     const unsigned kk = (unsigned)(j * nx + i);
     const R h = hin[kk];
-    R qx = qxin[kk], qy = qyin[kk];
+    qx = qxin[kk];
+    qy = qyin[kk];
     const R nm = p.manning ? p.manning[kk] : p.n_scalar;
     if (nm > R(0)) {
       R dqx, dqy;
@@ -1256,60 +1223,56 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
     const R sw = zvat(p, i, j, dT), se = zvat(p, i + 1, j, dT);
     const R nw = zvat(p, i, j + 1, dT), ne = zvat(p, i + 1, j + 1, dT);
     const int r = bb * RX + ab;
+    const R rr = frcp(fmaxr(h, Tiny<R>::v));
     sm.h[r] = h;
-    sm.qx[r] = qx;
-    sm.qy[r] = qy;
+    sm.u[r] = h > ht ? qx * rr : R(0);
+    sm.v[r] = h > ht ? qy * rr : R(0);
     sm.z0[r] = R(0.25) * ((ne + sw) + (nw + se));  // eq 8, diagonal pairs
   };
   const int ca = tid % TX + 1, cb = tid / TX + 1, cpos = cb * RX + ca;
-  load(ca, cb);
+  R qx0, qy0;
+  load(ca, cb, qx0, qy0);
   if (tid < NRING) {
     int ab, bb;
     if (tid < TY) { ab = 0; bb = tid + 1; }
     else if (tid < 2 * TY) { ab = TX + 1; bb = tid - TY + 1; }
     else if (tid < 2 * TY + TX) { ab = tid - 2 * TY + 1; bb = 0; }
     else { ab = tid - 2 * TY - TX + 1; bb = TY + 1; }
-    load(ab, bb);
+    R qxr, qyr;
+    load(ab, bb, qxr, qyr);
   }
   __syncthreads();
 
-  double led_in = 0.0, led_out = 0.0, led_clip = 0.0;
+  double led_in = 0.0, led_out = 0.0;
   const double wflux = dt * p.dxd;
-  auto vel = [&](int r, R& u, R& v) {
-    const R h = sm.h[r];
-    const R rr = frcp(fmaxr(h, Tiny<R>::v));
-    u = h > ht ? sm.qx[r] * rr : R(0);
-    v = h > ht ? sm.qy[r] * rr : R(0);
-  };
   // HLL through face f of a line (x: f between cells f-1 and f of row `line`; y: f
-  // between rows f-1 and f of column `line`); r is the box position of cell f, st the
-  // box step across the face; the flux goes to sm.f at r, in (mass, x-mom, y-mom)
+  // between rows f-1 and f of column `line`); r is the box position of cell f; the flux
+  // goes to sm.f at r, in (mass, x-mom, y-mom)
   auto face = [&](bool xdir, int f, int line, int r) {
     const int nf = xdir ? nx : ny;
-    if (line >= (xdir ? ny : nx) || f > nf) return;
+    if (EDGE && (line >= (xdir ? ny : nx) || f > nf)) return;
     const int st = xdir ? 1 : RX;
-    const int rl = f > 0 ? r - st : r, rr_ = f < nf ? r : r - st;
+    const int rl = (!EDGE || f > 0) ? r - st : r, rr_ = (!EDGE || f < nf) ? r : r - st;
     const R zl = sm.z0[rl], zr = sm.z0[rr_];
     const R zs = fmaxr(zl, zr);
-    R hl, zll, hr, zrr, ul, vl, ur, vr;
+    R hl, zll, hr, zrr;
     fv1_side(sm.h[rl], zl, zs, hl, zll);
     fv1_side(sm.h[rr_], zr, zs, hr, zrr);
-    vel(rl, ul, vl);
-    vel(rr_, ur, vr);
     // normal frame: x faces (h, u, v), y faces (h, v, u)
-    R nl = xdir ? ul : vl, tl = xdir ? vl : ul, nr = xdir ? ur : vr, tr = xdir ? vr : ur;
+    R nl = xdir ? sm.u[rl] : sm.v[rl], tl = xdir ? sm.v[rl] : sm.u[rl];
+    R nr = xdir ? sm.u[rr_] : sm.v[rr_], tr = xdir ? sm.v[rr_] : sm.u[rr_];
     const int eo = xdir ? 0 : 2 * ny;
-    if (f == 0) ghost(p, p.bface[eo + line], t, xdir, R(1), hr, nr, tr, hl, nl, tl);
-    else if (f == nf) ghost(p, p.bface[eo + (xdir ? ny : nx) + line], t, xdir, R(-1), hl, nl, tl, hr, nr, tr);
+    if (EDGE && f == 0) ghost(p, p.bface[eo + line], t, xdir, R(1), hr, nr, tr, hl, nl, tl);
+    else if (EDGE && f == nf) ghost(p, p.bface[eo + (xdir ? ny : nx) + line], t, xdir, R(-1), hl, nl, tl, hr, nr, tr);
     R o3[3];
     hll(g, hl, nl, tl, hr, nr, tr, o3);
     sm.f[0][r] = o3[0];
     sm.f[1][r] = xdir ? o3[1] : o3[2];  // x-momentum is tangential on a y-face
     sm.f[2][r] = xdir ? o3[2] : o3[1];
-    if (f == 0) {
+    if (EDGE && f == 0) {
       const double m = double(o3[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
-    } else if (f == nf) {
+    } else if (EDGE && f == nf) {
       const double m = -double(o3[0]) * wflux;
       if (m > 0) led_in += m; else led_out -= m;
     }
@@ -1326,14 +1289,14 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
   // ---- phase 2: x faces (each west face once; the tile's east faces by halo items) ----
   if (active) face(true, ci, cj, cpos);
   if (tid < TY) {
-    if (i0 + TX <= nx) face(true, i0 + TX, j0 + tid, (tid + 1) * RX + TX + 1);
+    if (!EDGE || i0 + TX <= nx) face(true, i0 + TX, j0 + tid, (tid + 1) * RX + TX + 1);
   }
-  if (active && ci == nx - 1 && i0 + TX > nx) face(true, nx, cj, cpos + 1);  // cut tile
+  if (EDGE && active && ci == nx - 1 && i0 + TX > nx) face(true, nx, cj, cpos + 1);  // cut tile
   __syncthreads();
   if (active) {
     R hE, zE, hW, zW;
-    side(cpos + 1, ci < nx - 1, hE, zE);
-    side(cpos - 1, ci > 0, hW, zW);
+    side(cpos + 1, !EDGE || ci < nx - 1, hE, zE);
+    side(cpos - 1, !EDGE || ci > 0, hW, zW);
     L0 = -(sm.f[0][cpos + 1] - sm.f[0][cpos]) * idx;
     L1 = -(sm.f[1][cpos + 1] - sm.f[1][cpos]) * idx - g * R(0.5) * (hE + hW) * (zE - zW) * idx;
     L2 = -(sm.f[2][cpos + 1] - sm.f[2][cpos]) * idx;
@@ -1343,24 +1306,26 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
   // ---- phase 3: y faces, then L0 and the forward-Euler update ----
   if (active) face(false, cj, ci, cpos);
   if (tid >= 64 && tid < 64 + TX) {
-    if (j0 + TY <= ny) face(false, j0 + TY, i0 + tid - 64, (TY + 1) * RX + tid - 64 + 1);
+    if (!EDGE || j0 + TY <= ny) face(false, j0 + TY, i0 + tid - 64, (TY + 1) * RX + tid - 64 + 1);
   }
-  if (active && cj == ny - 1 && j0 + TY > ny) face(false, ny, ci, cpos + RX);  // cut tile
+  if (EDGE && active && cj == ny - 1 && j0 + TY > ny) face(false, ny, ci, cpos + RX);  // cut tile
   __syncthreads();
   double my_dtc = __longlong_as_double((long long)INF_BITS);
+  double led_clip = 0.0;
   if (active) {
     R hN, zN, hS, zS;
-    side(cpos + RX, cj < ny - 1, hN, zN);
-    side(cpos - RX, cj > 0, hS, zS);
+    side(cpos + RX, !EDGE || cj < ny - 1, hN, zN);
+    side(cpos - RX, !EDGE || cj > 0, hS, zS);
     L0 += -(sm.f[0][cpos + RX] - sm.f[0][cpos]) * idx;
     L1 += -(sm.f[1][cpos + RX] - sm.f[1][cpos]) * idx;
     L2 += -(sm.f[2][cpos + RX] - sm.f[2][cpos]) * idx - g * R(0.5) * (hN + hS) * (zN - zS) * idx;
-    R u0 = h + dtr * L0, u1 = sm.qx[cpos] + dtr * L1, u2 = sm.qy[cpos] + dtr * L2;
-    if (u0 < R(0)) {
-      led_clip += -double(u0) * p.dxd * p.dxd;
-      u0 = R(0);
-    }
-    if (!(u0 > ht)) u1 = u2 = R(0);
+    R u0 = h + dtr * L0, u1 = qx0 + dtr * L1, u2 = qy0 + dtr * L2;
+    const bool neg = u0 < R(0);  // clip (booking the mass), branch-free
+    led_clip = neg ? -double(u0) * p.dxd * p.dxd : 0.0;
+    u0 = neg ? R(0) : u0;
+    const bool dry = !(u0 > ht);
+    u1 = dry ? R(0) : u1;
+    u2 = dry ? R(0) : u2;
     if ((u0 + u1 + u2) != (u0 + u1 + u2)) atomicOr(&ctl->health, 1);
     p.vbuf[ck] = u0;
     (p.vbuf + 3 * n)[ck] = u1;
@@ -1368,20 +1333,20 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
     my_dtc = cell_dtc(p, u0, R(0), R(0), u1, u2);
   }
   const int lane = tid & 63, wv = tid >> 6;
-  // ledger terms exist only where a tile touches the domain edge or a depth was clipped
-  const bool edge_tile = i0 == 0 || j0 == 0 || i0 + TX >= nx || j0 + TY >= ny;
-  if (edge_tile || __any(led_clip != 0.0)) {
-    const double r_in = wave_sum(led_in), r_out = wave_sum(led_out), r_clip = wave_sum(led_clip);
-    if (lane == 0) {
-      sm.red[wv][0] = r_in;
-      sm.red[wv][1] = r_out;
-      sm.red[wv][2] = r_clip;
-    }
-  } else if (lane == 0) {
-    sm.red[wv][0] = sm.red[wv][1] = sm.red[wv][2] = 0.0;
+  // boundary-flux ledger terms exist only in edge tiles
+  const double r_clip = wave_sum(led_clip);
+  double r_in = 0.0, r_out = 0.0;
+  if (EDGE) {
+    r_in = wave_sum(led_in);
+    r_out = wave_sum(led_out);
   }
   const double r_dt = wave_min(my_dtc);
-  if (lane == 0) sm.red[wv][3] = r_dt;
+  if (lane == 0) {
+    sm.red[wv][0] = r_in;
+    sm.red[wv][1] = r_out;
+    sm.red[wv][2] = r_clip;
+    sm.red[wv][3] = r_dt;
+  }
   __syncthreads();
   if (tid == 0) {
     double ai = 0, ao = 0, ac = 0, m = __longlong_as_double((long long)INF_BITS);
@@ -1404,6 +1369,65 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
     if (m != __longlong_as_double((long long)INF_BITS))
       cand_post(ctl->dtr[(k + 1) % 3], tile, m);
   }
+}
+
+template <typename R, typename S>
+__global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
+  using SM = SmemFV1<R, S>;
+  constexpr int TX = SM::TX, TY = SM::TY, NT = SM::NT;
+  constexpr int NRING = 2 * (TX + TY);
+  static_assert(NT % 64 == 0 && NRING <= NT && TY <= 64 && 64 + TX <= NT,
+                "tile must give whole waves and room for the halo items");
+  __shared__ SM sm;
+  const int b = blockIdx.x;
+  const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
+  if (tile >= p.n_tiles) return;
+  const int tid = threadIdx.x;
+  const int nx = p.nx, ny = p.ny;
+  const long long n = p.n;
+  const int i0 = (tile % p.tiles_x) * TX, j0 = (tile / p.tiles_x) * TY;
+
+  // the step's time step from the ring slot of this step
+  Ctrl* ctl = p.ctrl;
+  const int a = p.parity, o = 1 - p.parity;
+  const long long k = ctl->step[a];
+  const double t = uniform(ctl->t[a]);
+  const double mm = cand_read(ctl->dtr[k % 3]);
+  double dt = (mm == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * mm;
+  const double dt_cfl = dt;
+  if (p.dt_max > 0.0 && p.dt_max < dt) dt = p.dt_max;
+  double t_next = t + dt;
+  if (p.t_end - t <= dt) {
+    dt = p.t_end - t;
+    t_next = p.t_end;
+  }
+  if (!(dt > 0.0)) {  // past t_end: carry the state over
+    const int ci = i0 + tid % TX, cj = j0 + tid / TX;
+    if (ci < nx && cj < ny) {
+      const unsigned ck = (unsigned)(cj * nx + ci);
+      (p.vbuf)[ck] = p.uin[ck];
+      (p.vbuf + 3 * n)[ck] = p.uin[3 * n + ck];
+      (p.vbuf + 6 * n)[ck] = p.uin[6 * n + ck];
+    }
+    if (tile == 0 && tid == 0) {
+      ctl->t[o] = t;
+      ctl->step[o] = k;
+      ctl->dt_used[a] = 0.0;
+    }
+    return;
+  }
+  if (tile == 0 && tid == 0) {
+    ctl->t[o] = t_next;
+    ctl->step[o] = k + 1;
+    ctl->dt_used[a] = dt;
+    cand_clear(ctl->dtr[(k + 2) % 3]);
+    if (dt_cfl < 1e-12) atomicOr(&ctl->health, 2);
+  }
+  const bool interior = i0 >= 1 && j0 >= 1 && i0 + TX + 1 <= nx && j0 + TY + 1 <= ny;
+  if (interior)
+    fv1_body<R, S, false>(p, sm, tile, i0, j0, t, dt, k, t_next);
+  else
+    fv1_body<R, S, true>(p, sm, tile, i0, j0, t, dt, k, t_next);
 }
 
 // ---------------------------------------------------------------------------------
