@@ -1359,7 +1359,9 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
   const size_t st = 9 * c->n * sizeof(double);
   const int nseg = (int)c->knot_count.size();
   const size_t nfs = 2 * ((size_t)c->cfg.nx + c->cfg.ny);
-  const unsigned cb = (unsigned)((n + 255) / 256);
+  // the adjoint kernel's 32 x 8 tiles
+  const unsigned cb = (unsigned)(((c->cfg.nx + dg2k::ADJ_TX - 1) / dg2k::ADJ_TX) *
+                                 ((c->cfg.ny + dg2k::ADJ_TY - 1) / dg2k::ADJ_TY));
   const unsigned gb = (unsigned)((tp->ng + 63) / 64);
   // reset
   {
@@ -1393,11 +1395,11 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
       // stage 2: nu2 = lam / 2 + (dL/dV)(U^int)^T (dt lam / 2)
       dg2k::AdjArgs a2{tp->segI + r, tp->lam, 0.5 * dt, tp->t[k] + dt, tp->lam, 0.5, nullptr,
                        nullptr, 0.0, nullptr, tp->nu2, tp->gq + ((size_t)k * 2 + 1) * nfs, tp->regime};
-      hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(256), 0, sm, p, a2);
+      hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(dg2k::ADJ_TX * dg2k::ADJ_TY), 0, sm, p, a2);
       // stage 1 and friction: lam <- (dF/dU)^T (lam / 2 + nu2 + (dL/dV)(V^n)^T (dt nu2))
       dg2k::AdjArgs a1{tp->segV + r, tp->nu2, dt, tp->t[k], tp->lam, 0.5, tp->nu2,
                        tp->seg + r, dt, tp->gman, tp->lam, tp->gq + ((size_t)k * 2) * nfs, tp->regime};
-      hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(256), 0, sm, p, a1);
+      hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(dg2k::ADJ_TX * dg2k::ADJ_TY), 0, sm, p, a1);
       if (tp->ng > 0)
         hipLaunchKernelGGL(dg2k::gauge_seed_kernel, dim3(gb), dim3(64), 0, sm, tp->lam, tp->gidx, tp->ng,
                            tp->dj + (size_t)k * tp->ng);

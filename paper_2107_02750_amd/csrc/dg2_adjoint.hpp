@@ -245,29 +245,55 @@ struct AdjArgs {
   int* regime;          // out: |= violation bits
 };
 
-__global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArgs a) {
+// the adjoint works on 32 x 8 tiles: the stage input and mu of the tile and a one-cell
+// halo are staged in LDS, so the neighbour reads of the face terms are LDS reads
+constexpr int ADJ_TX = 32, ADJ_TY = 8, ADJ_RX = ADJ_TX + 2, ADJ_RB = ADJ_RX * (ADJ_TY + 2);
+struct AdjSmem {
+  double v[9][ADJ_RB];  // stage input V
+  double m[9][ADJ_RB];  // mu = alpha lam
+};
+
+__global__ __launch_bounds__(ADJ_TX * ADJ_TY) void adj_stage_kernel(Params<double> p, AdjArgs a) {
+  __shared__ AdjSmem sm;
   const long long n = p.n;
   const int nx = p.nx, ny = p.ny;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const int i = int(c % nx), j = int(c / nx);
+  const int tiles_x = (nx + ADJ_TX - 1) / ADJ_TX;
+  const int i0 = (int(blockIdx.x) % tiles_x) * ADJ_TX, j0 = (int(blockIdx.x) / tiles_x) * ADJ_TY;
+  const int tid = threadIdx.x;
+  for (int r = tid; r < ADJ_RB; r += ADJ_TX * ADJ_TY) {  // box cells, clamped to the domain
+    int bi = i0 - 1 + r % ADJ_RX, bj = j0 - 1 + r / ADJ_RX;
+    bi = bi < 0 ? 0 : (bi >= nx ? nx - 1 : bi);
+    bj = bj < 0 ? 0 : (bj >= ny ? ny - 1 : bj);
+    const long long k = (long long)bj * nx + bi;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      sm.v[q][r] = a.V[q * n + k];
+      sm.m[q][r] = a.alpha * a.lam[q * n + k];
+    }
+  }
+  __syncthreads();
+  const int i = i0 + tid % ADJ_TX, j = j0 + tid / ADJ_TX;
+  if (i >= nx || j >= ny) return;  // no barrier follows
+  const long long c = (long long)j * nx + i;
+  const int cpos = (tid / ADJ_TX + 1) * ADJ_RX + tid % ADJ_TX + 1;
   const double g = p.g, ht = p.h_tol, s3 = K<double>::s3;
   const double idx = 1.0 / p.dx, cc = -s3 * idx, i2s3 = K<double>::inv_2s3;
   const double k2s3 = 2.0 * s3 * g * idx;
   const double slack = dsqrt(p.gd * p.htd);
-  auto V = [&](long long k, int q) { return a.V[q * n + k]; };
-  auto mu = [&](long long k, int q) { return a.alpha * a.lam[q * n + k]; };
+  // box position of a cell: the cell itself or one of its four neighbours
+  auto V = [&](int pos, int q) { return sm.v[q][pos]; };
+  auto mu = [&](int pos, int q) { return sm.m[q][pos]; };
   auto zvv = [&](int iv, int jv) { return p.zv[(long long)jv * (nx + 1) + iv]; };
-  auto umean = [&](long long k, bool xv) {
-    const double h0 = V(k, 0);
-    return h0 > ht ? V(k, xv ? 3 : 6) * frcp(h0) : 0.0;
+  auto umean = [&](int pos, bool xv) {
+    const double h0 = V(pos, 0);
+    return h0 > ht ? V(pos, xv ? 3 : 6) * frcp(h0) : 0.0;
   };
   // the cell's own coefficients, cotangents and mean velocities, read once
   double vc[9], mc[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    vc[q] = V(c, q);
-    mc[q] = mu(c, q);
+    vc[q] = V(cpos, q);
+    mc[q] = mu(cpos, q);
   }
   const double u0c = vc[0] > ht ? vc[3] * frcp(vc[0]) : 0.0;
   const double v0c = vc[0] > ht ? vc[6] * frcp(vc[0]) : 0.0;
@@ -293,7 +319,7 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(Params<double> p, AdjArg
     const int va = xdir ? (high ? i + 1 : i) : i, vb = xdir ? j : (high ? j + 1 : j);  // first vertex
     const double zf = 0.5 * (zvv(va, vb) + (xdir ? zvv(va, vb + 1) : zvv(va + 1, vb)));
     const bool inside = ni >= 0 && ni < nx && nj >= 0 && nj < ny;
-    const long long nk = inside ? (long long)nj * nx + ni : c;
+    const int nk = inside ? cpos + (xdir ? (high ? 1 : -1) : (high ? ADJ_RX : -ADJ_RX)) : cpos;
     // own side after the revision (both sides share the face bed in this regime)
     const double ro = frcp(ho);
     const double hs = fmax0((ho + zf) - zf), uo = qxo * ro, vo = qyo * ro;
