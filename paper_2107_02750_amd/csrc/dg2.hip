@@ -1178,6 +1178,8 @@ struct dg2_tape {
   double* gh;                  // gauge depths (n_steps + 1) x ng
   double* dj;                  // dJ/dh on the device
   int* gidx;
+  int* gmap;                   // per cell: its first gauge, or -1
+  int* gnext;                  // per gauge: the next gauge on the same cell, or -1
   int* regime;
   dg2k::Ctrl* ctrl;            // the tape's own control block for recomputation
   double* ledger;
@@ -1300,12 +1302,23 @@ int dg2_tape_create(dg2_ctx* c, int32_t n_steps, const double* dts, const int32_
   if (e == hipSuccess) e = hipMalloc((void**)&tp->gh, (size_t)(n_steps + 1) * std::max(n_gauges, 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->dj, (size_t)(n_steps + 1) * std::max(n_gauges, 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->gidx, std::max(n_gauges, 1) * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->gmap, c->n * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->gnext, std::max(n_gauges, 1) * sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->regime, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->ctrl, sizeof(dg2k::Ctrl));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->ledger, (size_t)c->L.n_tiles * 4 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->d_t, (size_t)(n_steps + 1) * sizeof(double));
   if (e == hipSuccess && n_gauges > 0)
     e = hipMemcpyAsync(tp->gidx, gauges, n_gauges * sizeof(int), hipMemcpyHostToDevice, c->stream);
+  // the gauges of each cell as a chain in gauge order (the adjoint adds their seeds)
+  std::vector<int> gmap(c->n, -1), gnext(std::max(n_gauges, 1), -1);
+  for (int g = n_gauges - 1; g >= 0; --g) {
+    gnext[g] = gmap[gauges[g]];
+    gmap[gauges[g]] = g;
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(tp->gmap, gmap.data(), c->n * sizeof(int), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(tp->gnext, gnext.data(), gnext.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     g_init_err = std::string("tape buffers: ") + hipGetErrorString(e);
@@ -1394,15 +1407,16 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
       Params<double> p = params<double>(c);
       // stage 2: nu2 = lam / 2 + (dL/dV)(U^int)^T (dt lam / 2)
       dg2k::AdjArgs a2{tp->segI + r, tp->lam, 0.5 * dt, tp->t[k] + dt, tp->lam, 0.5, nullptr,
-                       nullptr, 0.0, nullptr, tp->nu2, tp->gq + ((size_t)k * 2 + 1) * nfs, tp->regime};
+                       nullptr, 0.0, nullptr, nullptr, nullptr, nullptr,
+                       tp->nu2, tp->gq + ((size_t)k * 2 + 1) * nfs, tp->regime};
       hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(dg2k::ADJ_TX * dg2k::ADJ_TY), 0, sm, p, a2);
-      // stage 1 and friction: lam <- (dF/dU)^T (lam / 2 + nu2 + (dL/dV)(V^n)^T (dt nu2))
+      // stage 1 and friction: lam <- (dF/dU)^T (lam / 2 + nu2 + (dL/dV)(V^n)^T (dt nu2)),
+      // then the misfit's seeds of the gauges at step k
       dg2k::AdjArgs a1{tp->segV + r, tp->nu2, dt, tp->t[k], tp->lam, 0.5, tp->nu2,
-                       tp->seg + r, dt, tp->gman, tp->lam, tp->gq + ((size_t)k * 2) * nfs, tp->regime};
+                       tp->seg + r, dt, tp->gman,
+                       tp->ng > 0 ? tp->gmap : nullptr, tp->gnext, tp->dj + (size_t)k * tp->ng,
+                       tp->lam, tp->gq + ((size_t)k * 2) * nfs, tp->regime};
       hipLaunchKernelGGL(dg2k::adj_stage_kernel, dim3(cb), dim3(dg2k::ADJ_TX * dg2k::ADJ_TY), 0, sm, p, a1);
-      if (tp->ng > 0)
-        hipLaunchKernelGGL(dg2k::gauge_seed_kernel, dim3(gb), dim3(64), 0, sm, tp->lam, tp->gidx, tp->ng,
-                           tp->dj + (size_t)k * tp->ng);
       THIPC(tp, hipGetLastError());
     }
   }
@@ -1464,7 +1478,7 @@ void dg2_tape_destroy(dg2_tape* tp) {
   if (!tp) return;
   (void)hipStreamSynchronize(tp->c->stream);
   for (void* b : {(void*)tp->ckpt, (void*)tp->seg, (void*)tp->segV, (void*)tp->segI, (void*)tp->lam,
-                  (void*)tp->nu2, (void*)tp->gman, (void*)tp->gq, (void*)tp->gh, (void*)tp->dj, (void*)tp->gidx,
+                  (void*)tp->nu2, (void*)tp->gman, (void*)tp->gq, (void*)tp->gh, (void*)tp->dj, (void*)tp->gidx, (void*)tp->gmap, (void*)tp->gnext,
                   (void*)tp->regime, (void*)tp->ctrl, (void*)tp->ledger, (void*)tp->d_t})
     if (b) (void)hipFree(b);
   delete tp;

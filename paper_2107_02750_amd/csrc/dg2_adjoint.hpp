@@ -239,6 +239,9 @@ struct AdjArgs {
   const double* U_fr;   // friction adjoint of the step from state U_fr, or nullptr
   double dt_fr;
   double* gman;         // dJ/dn per cell (accumulated) with U_fr
+  const int* gmap;      // with gmap: each cell's gauges (first gauge, then gnext per
+  const int* gnext;     // gauge; -1 ends) add their seed[g] to the output's mean depth
+  const double* seed;
   double* out;          // 9 planes; may be lam_c itself (each cell reads its own first)
   double* gqf;          // out: dJ/dQ of each inflow boundary face (slots as the face
                         // codes: W[ny], E[ny], S[nx], N[nx]), summed per segment later
@@ -473,6 +476,8 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY) void adj_stage_kernel(Params<doubl
     const double gn = adj_friction_cell(p, a.U_fr, c, a.dt_fr, nu);
     if (a.gman) a.gman[c] += gn;
   }
+  if (a.gmap)
+    for (int gg = a.gmap[c]; gg >= 0; gg = a.gnext[gg]) nu[0] += a.seed[gg];
 #pragma unroll
   for (int q = 0; q < 9; ++q) a.out[q * n + c] = nu[q];
   if (bad) atomicOr(a.regime, bad);
