@@ -317,6 +317,8 @@ def main():
                     help="only the FP64 timed region (for profiler runs)")
     ap.add_argument("--fv1-only", action="store_true",
                     help="only the FV1 leg, as its own JSON line (for profiler runs)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint leg, as its own JSON line (for profiler runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -337,6 +339,13 @@ def main():
             torch.cuda.synchronize()
         print(json.dumps({"metric": "FV1 cell-updates/s (forward-Euler step, FP64)",
                           "value": r["fp64"]["value"], "unit": "cell-updates/s", "fv1": r}),
+              flush=True)
+        return
+
+    if args.adjoint_only:
+        r = adjoint_leg(dg2, S, args.adjoint_n, args.adjoint_steps)
+        print(json.dumps({"metric": "adjoint time over forward time (gauge misfit gradients)",
+                          "value": r["adjoint_over_forward"], "unit": "ratio", "adjoint": r}),
               flush=True)
         return
 
