@@ -326,13 +326,13 @@ __device__ __forceinline__ void friction_inc(R gn2dt, R ht, R h, R qx, R qy, R& 
   const R s2 = u * u + v * v;
   const bool act = wet && s2 > R(0);
   const R rs = frsq(fmaxr(s2, Tiny<R>::v));  // 1/|u|
-  const R w = gn2dt * (y3 * y);          // dt g n^2 h^(-4/3)
-  const R a = w * u * u * rs, b = w * v * v * rs;
-  const R ab = a + b;
-  const R d1 = R(1) + R(2) * a + b, d2 = R(1) + a + R(2) * b;
-  const R inv = frcp(d1 * d2);
-  dqx = act ? -qx * ab * d2 * inv : R(0);
-  dqy = act ? -qy * ab * d1 * inv : R(0);
+  const R m = gn2dt * (y3 * y) * rs;     // dt g n^2 h^(-4/3) / |u|
+  const R a = m * (u * u), b = m * (v * v);
+  const R ab = a + b;                    // dt g n^2 h^(-4/3) |u|
+  const R d1 = (R(1) + a) + ab, d2 = (R(1) + b) + ab;
+  const R P = ab * frcp(d1 * d2);
+  dqx = act ? -qx * d2 * P : R(0);
+  dqy = act ? -qy * d1 * P : R(0);
 }
 
 // datum of the tile holding cell (i, j) (0 without a datum)
