@@ -1,0 +1,30 @@
+"""Host-side checks of bench.py: the one-GPU guard and the algorithmic byte counts that
+the roofline uses (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_algorithmic_bytes_per_stage():
+    n = 1024 * 1024
+    # stage 1: U^n (9) + bed vertex (1) read, U^int (9) written
+    assert bench.stage_bytes("stage1", n, 8) == 19 * 8 * n
+    # stage 2: U^n (9), U^int (9), bed (1) read, U^{n+1} (9) written
+    assert bench.stage_bytes("stage2", n, 8) == 28 * 8 * n
+    # 376 B per cell-step in FP64, 188 B in FP32
+    assert (bench.stage_bytes("stage1", 1, 8) + bench.stage_bytes("stage2", 1, 8)) == 376
+    assert (bench.stage_bytes("stage1", 1, 4) + bench.stage_bytes("stage2", 1, 4)) == 188
+    # what the kernels move by design: V^n written by stage 1 and read by stage 2
+    assert bench.stage_bytes("stage1", 1, 8, bench.IMPL_VALUES) == 224
