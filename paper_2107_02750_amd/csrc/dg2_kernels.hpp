@@ -29,9 +29,9 @@ struct Shape {
   static constexpr int X = TX_, Y = TY_, B1 = B1_, B2 = B2_;
 };
 constexpr int N_SHAPES = 4;
-// FP64: 32x8 (default), 16x16, 16x8, 64x4; FP32: 64x8 (default), 32x16, 32x8, 16x16;
+// FP64: 16x16 (default), 32x8, 16x8, 64x4; FP32: 64x8 (default), 32x16, 32x8, 16x16;
 // columns: TX, TY, B1, B2
-constexpr int SHAPE64[N_SHAPES][4] = {{32, 8, 4, 4}, {16, 16, 4, 4}, {16, 8, 1, 1}, {64, 4, 1, 1}};
+constexpr int SHAPE64[N_SHAPES][4] = {{16, 16, 4, 4}, {32, 8, 4, 4}, {16, 8, 1, 1}, {64, 4, 1, 1}};
 constexpr int SHAPE32[N_SHAPES][4] = {{64, 8, 1, 1}, {32, 16, 1, 1}, {32, 8, 1, 1}, {16, 16, 1, 1}};
 
 // LDS geometry of a tile: the cell box has a 2-cell halo, the vertex box one more
