@@ -539,83 +539,48 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   }
 
   // ---- phase 1: the box (friction applied in stage 1) and its bed vertices ----
+  // Every global load of this phase is issued before any is waited on: the bed vertices
+  // (VITER per thread), the own cell and the thread's first halo item. Issued one after
+  // the other, they cost a memory round trip each.
   const R dT = (sizeof(R) == 4 && p.datum) ? p.datum[tile] : R(0);
-  // vertex (iv, jv) sits at box position (iv - i0 + 2, jv - j0 + 2); a clamped halo
-  // cell only uses vertices of in-domain cells, which lie in the box
-  for (int r = tid; r < VB; r += NT) {
-    int iv = i0 - 2 + r % VX, jv = j0 - 2 + r / VX;
-    if (EDGE) {
-      iv = iv < 0 ? 0 : (iv > nx ? nx : iv);
-      jv = jv < 0 ? 0 : (jv > ny ? ny : jv);
-    }
-    R z = p.zv[(unsigned)(jv * (nx + 1) + iv)];
-    if (sizeof(R) == 4 && p.datum) {  // to this tile's frame
-      const int oi = iv < nx ? iv : nx - 1, oj = jv < ny ? jv : ny - 1;
-      z += p.datum[(oj / TY) * p.tiles_x + oi / TX] - dT;
-    }
-    sm.zv[r] = z;
-  }
-  auto zb = [&](int iv, int jv) -> R { return sm.zv[(jv - j0 + 2) * VX + (iv - i0 + 2)]; };
   const R dtr = R(dt);
   const R* __restrict__ src = STAGE == 1 ? p.uin : p.ui;
-  // load box cell (a, bb), apply friction in stage 1 (npair: 0 centre only, 1 one Gauss
-  // pair whose slopes are picked by xdir, 2 both pairs, -1 none) and publish it
-  auto load_cell = [&](int a, int bb, int npair, bool xdir, R c[9]) {
-    const int r = bb * RX + a;
+  constexpr int VITER = (VB + NT - 1) / NT;
+  constexpr int NHALO = 2 * NRING + 4;  // halo items: first ring, second ring, corners
+  // vertex (iv, jv) sits at box position (iv - i0 + 2, jv - j0 + 2); a clamped halo
+  // cell only uses vertices of in-domain cells, which lie in the box
+  R zl[VITER];
+#pragma unroll
+  for (int k = 0; k < VITER; ++k) {
+    const int r = tid + k * NT;
+    zl[k] = R(0);
+    if (r < VB) {
+      int iv = i0 - 2 + r % VX, jv = j0 - 2 + r / VX;
+      if (EDGE) {
+        iv = iv < 0 ? 0 : (iv > nx ? nx : iv);
+        jv = jv < 0 ? 0 : (jv > ny ? ny : jv);
+      }
+      R z = p.zv[(unsigned)(jv * (nx + 1) + iv)];
+      if (sizeof(R) == 4 && p.datum) {  // to this tile's frame
+        const int oi = iv < nx ? iv : nx - 1, oj = jv < ny ? jv : ny - 1;
+        z += p.datum[(oj / TY) * p.tiles_x + oi / TX] - dT;
+      }
+      zl[k] = z;
+    }
+  }
+  auto zb = [&](int iv, int jv) -> R { return sm.zv[(jv - j0 + 2) * VX + (iv - i0 + 2)]; };
+  // cell index of box position (a, bb), clamped to the domain
+  auto cell_of = [&](int a, int bb) -> unsigned {
     int i = i0 - 2 + a, j = j0 - 2 + bb;
     if (EDGE) {
       i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
       j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
     }
-    const unsigned k = (unsigned)(j * nx + i);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) c[q] = (src + q * n)[k];
-    if (STAGE == 1 && npair >= 0) {
-      const R nm = p.manning ? p.manning[k] : p.n_scalar;
-      if (nm > R(0)) {
-        const R gn2dt = p.g * nm * nm * dtr;
-        R dx0, dy0;
-        friction_inc(gn2dt, ht, c[0], c[3], c[6], dx0, dy0);
-        if (npair == 2) {
-#pragma unroll
-          for (int d = 1; d <= 2; ++d) {
-            R dxp, dyp, dxm, dym;
-            friction_inc(gn2dt, ht, c[0] + c[d], c[3] + c[3 + d], c[6] + c[6 + d], dxp, dyp);
-            friction_inc(gn2dt, ht, c[0] - c[d], c[3] - c[3 + d], c[6] - c[6 + d], dxm, dym);
-            c[3 + d] += R(0.5) * (dxp - dxm);
-            c[6 + d] += R(0.5) * (dyp - dym);
-          }
-        } else if (npair == 1) {  // one pair; slopes selected, not indexed
-          const R h1 = xdir ? c[1] : c[2], qx1 = xdir ? c[4] : c[5], qy1 = xdir ? c[7] : c[8];
-          R dxp, dyp, dxm, dym;
-          friction_inc(gn2dt, ht, c[0] + h1, c[3] + qx1, c[6] + qy1, dxp, dyp);
-          friction_inc(gn2dt, ht, c[0] - h1, c[3] - qx1, c[6] - qy1, dxm, dym);
-          const R ex = R(0.5) * (dxp - dxm), ey = R(0.5) * (dyp - dym);
-          c[4] += xdir ? ex : R(0);
-          c[5] += xdir ? R(0) : ex;
-          c[7] += xdir ? ey : R(0);
-          c[8] += xdir ? R(0) : ey;
-        }
-        c[3] += dx0;
-        c[6] += dy0;
-      }
-    }
-    sm.c[0][r] = c[0];  // means only: the slopes stay with the thread that owns the cell
-    sm.c[1][r] = c[3];
-    sm.c[2][r] = c[6];
-    const bool wet = c[0] > ht;
-    const R rh = frcp(fmaxr(c[0], Tiny<R>::v));
-    sm.um[r] = wet ? c[3] * rh : R(0);
-    sm.vm[r] = wet ? c[6] * rh : R(0);
+    return (unsigned)(j * nx + i);
   };
-  // the own tile cell first (both Gauss pairs, the same path in every lane), then the
-  // halo: the first ring (one pair across the tile edge), the second ring (centre
-  // only) and the four first-ring corners (depth only)
-  R va[9], vb[9];  // the own cell and the thread's first-ring cell (ring items below)
-  load_cell(tid % TX + 2, tid / TX + 2, 2, true, va);
-  for (int h = tid; h < 2 * NRING + 4; h += NT) {
-    int a, bb, np;
-    bool xd;
+  // halo item h: its box position and friction points (npair: 0 centre only, 1 one
+  // Gauss pair whose slopes are picked by xdir, -1 none)
+  auto halo_item = [&](int h, int& a, int& bb, int& np, bool& xd) {
     if (h < NRING) {  // same numbering as the ring items below
       if (h < TY) { a = 1; bb = h + 2; xd = true; }
       else if (h < 2 * TY) { a = TX + 2; bb = h - TY + 2; xd = true; }
@@ -637,12 +602,75 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
       np = -1;
       xd = true;
     }
-    R tmp[9];
-    load_cell(a, bb, np, xd, tmp);
-    if (h < NRING) {  // first pass of this loop: h == tid, the thread's own ring item
+  };
+  auto load_raw = [&](unsigned k, R c[9], R& nm) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) vb[q] = tmp[q];
+    for (int q = 0; q < 9; ++q) c[q] = (src + q * n)[k];
+    nm = (STAGE == 1) ? (p.manning ? p.manning[k] : p.n_scalar) : R(0);
+  };
+  // apply friction in stage 1 (npair as above; 2: both pairs) and publish box cell (a, bb)
+  auto publish = [&](int a, int bb, int npair, bool xdir, R c[9], R nm) {
+    const int r = bb * RX + a;
+    if (STAGE == 1 && npair >= 0 && nm > R(0)) {
+      const R gn2dt = p.g * nm * nm * dtr;
+      R dx0, dy0;
+      friction_inc(gn2dt, ht, c[0], c[3], c[6], dx0, dy0);
+      if (npair == 2) {
+#pragma unroll
+        for (int d = 1; d <= 2; ++d) {
+          R dxp, dyp, dxm, dym;
+          friction_inc(gn2dt, ht, c[0] + c[d], c[3] + c[3 + d], c[6] + c[6 + d], dxp, dyp);
+          friction_inc(gn2dt, ht, c[0] - c[d], c[3] - c[3 + d], c[6] - c[6 + d], dxm, dym);
+          c[3 + d] += R(0.5) * (dxp - dxm);
+          c[6 + d] += R(0.5) * (dyp - dym);
+        }
+      } else if (npair == 1) {  // one pair; slopes selected, not indexed
+        const R h1 = xdir ? c[1] : c[2], qx1 = xdir ? c[4] : c[5], qy1 = xdir ? c[7] : c[8];
+        R dxp, dyp, dxm, dym;
+        friction_inc(gn2dt, ht, c[0] + h1, c[3] + qx1, c[6] + qy1, dxp, dyp);
+        friction_inc(gn2dt, ht, c[0] - h1, c[3] - qx1, c[6] - qy1, dxm, dym);
+        const R ex = R(0.5) * (dxp - dxm), ey = R(0.5) * (dyp - dym);
+        c[4] += xdir ? ex : R(0);
+        c[5] += xdir ? R(0) : ex;
+        c[7] += xdir ? ey : R(0);
+        c[8] += xdir ? R(0) : ey;
+      }
+      c[3] += dx0;
+      c[6] += dy0;
     }
+    sm.c[0][r] = c[0];  // means only: the slopes stay with the thread that owns the cell
+    sm.c[1][r] = c[3];
+    sm.c[2][r] = c[6];
+    const bool wet = c[0] > ht;
+    const R rh = frcp(fmaxr(c[0], Tiny<R>::v));
+    sm.um[r] = wet ? c[3] * rh : R(0);
+    sm.vm[r] = wet ? c[6] * rh : R(0);
+  };
+  // the own tile cell (both Gauss pairs, the same path in every lane) and the thread's
+  // halo item: the first ring (one pair across the tile edge), the second ring (centre
+  // only) or the four first-ring corners (depth only)
+  R va[9], vb[9];  // the own cell and the thread's halo item (the ring items below)
+  R nma, nmb = R(0);
+  load_raw(cell_of(tid % TX + 2, tid / TX + 2), va, nma);
+  int ha = 0, hbb = 0, hnp = -1;
+  bool hxd = true;
+  const bool has_item = tid < NHALO;
+  if (has_item) {
+    halo_item(tid, ha, hbb, hnp, hxd);
+    load_raw(cell_of(ha, hbb), vb, nmb);
+  }
+#pragma unroll
+  for (int k = 0; k < VITER; ++k)
+    if (tid + k * NT < VB) sm.zv[tid + k * NT] = zl[k];
+  publish(tid % TX + 2, tid / TX + 2, 2, true, va, nma);
+  if (has_item) publish(ha, hbb, hnp, hxd, vb, nmb);
+  for (int h = tid + NT; h < NHALO; h += NT) {  // shapes with more halo items than threads
+    int a, bb, np;
+    bool xd;
+    halo_item(h, a, bb, np, xd);
+    R tmp[9], nm;
+    load_raw(cell_of(a, bb), tmp, nm);
+    publish(a, bb, np, xd, tmp, nm);
   }
   __syncthreads();
   for (int r = tid; r < RB; r += NT) {  // bed means of the box cells (eq 8, diagonal pairs)
