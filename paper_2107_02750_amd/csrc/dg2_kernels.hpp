@@ -972,15 +972,15 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   yface(ci, cj, cpos, ss_, active, tb * TX + ta);
   if (has_b && rb_side == 1) xface(ri, rj, rpos, sb_, b_in, (rb_b - 2) * (TX + 1) + TX);
   if (has_b && rb_side == 3) yface(ri, rj, rpos, sb_, b_in, TY * TX + (rb_a - 2));
+  if (STAGE == 2 && !kPrefetch && active) {  // V^n of the own cell: in flight across the barrier
+#pragma unroll
+    for (int q = 0; q < 9; ++q) vn[q] = (p.vbuf + q * n)[ck];
+  }
   __syncthreads();
 
   // ---- phase 3: L, the stage update, and the per-block reductions ----
   double my_dtc = __longlong_as_double((long long)INF_BITS);
   if (active) {
-    if (STAGE == 2 && !kPrefetch) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) vn[q] = (p.vbuf + q * n)[ck];
-    }
     const int xw = tb * (TX + 1) + ta, ys = tb * TX + ta;
     const R fw[3] = {sm.fx[0][xw], sm.fx[1][xw], sm.fx[2][xw]};
     const R fe[3] = {sm.fx[0][xw + 1], sm.fx[1][xw + 1], sm.fx[2][xw + 1]};
