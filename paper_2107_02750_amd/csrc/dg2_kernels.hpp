@@ -80,6 +80,7 @@ struct Ctrl {
 
 // the candidate's value: min over its slots (every lane of the wave must take part)
 __device__ __forceinline__ double cand_read(const Cand& c);
+__device__ __forceinline__ double wave_min(double x);
 // post a block's candidate / clear all slots (one thread)
 __device__ __forceinline__ void cand_post(Cand& c, int block, double m) {
   atomicMin(&c.s[(block % NSLOT) * SLOT_STRIDE], (unsigned long long)__double_as_longlong(m));
@@ -220,12 +221,24 @@ __device__ __forceinline__ double uniform(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// the step's time step, identical in every block of both stage launches
+// the step's time step, identical in every block of both stage launches, in two parts
+// so that a kernel can put its own loads between them: the loads (the step's start
+// time; lane k < NSLOT one CFL slot), then the arithmetic
+struct StepLoads {
+  double t, slot;
+};
 template <typename R>
-__device__ __forceinline__ void step_time(const Params<R>& p, double& t, double& dt, double& t_next,
-                                          double& dt_cfl) {
-  t = uniform(p.ctrl->t[p.parity]);
-  const double m = cand_read(p.ctrl->dtc[p.parity]);
+__device__ __forceinline__ StepLoads step_loads(const Params<R>& p) {
+  const int lane = threadIdx.x & 63;
+  const Cand& c = p.ctrl->dtc[p.parity];
+  return StepLoads{p.ctrl->t[p.parity], lane < NSLOT ? __longlong_as_double((long long)c.s[lane * SLOT_STRIDE])
+                                                      : __longlong_as_double((long long)INF_BITS)};
+}
+template <typename R>
+__device__ __forceinline__ void step_time(const Params<R>& p, const StepLoads& l, double& t, double& dt,
+                                          double& t_next, double& dt_cfl) {
+  t = uniform(l.t);
+  const double m = wave_min(l.slot);
   double d = (m == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * m;
   dt_cfl = d;
   if (p.dt_fix > 0.0) {
@@ -473,17 +486,13 @@ __device__ __forceinline__ double wave_min(double x) {
   return dmin2(lane_value(x, 0), lane_value(x, 32));
 }
 
-// every thread reads the slots itself (uniform loads): a cross-lane reduction here
-// would share its lane-address arithmetic with the reductions at the end of the stage
-// kernels, which then holds those registers through the whole kernel
+// lane k < NSLOT reads slot k (one memory round trip for all of them) and the wave
+// takes the minimum with the swizzle reduction, which holds no lane-address registers
 __device__ __forceinline__ double cand_read(const Cand& c) {
-  unsigned long long m = c.s[0];
-#pragma unroll
-  for (int q = 1; q < NSLOT; ++q) {
-    const unsigned long long v = c.s[q * SLOT_STRIDE];
-    m = v < m ? v : m;  // positive doubles order like their bit patterns
-  }
-  return __longlong_as_double((long long)m);
+  const int lane = threadIdx.x & 63;
+  const double v = lane < NSLOT ? __longlong_as_double((long long)c.s[lane * SLOT_STRIDE])
+                                : __longlong_as_double((long long)INF_BITS);
+  return wave_min(v);
 }
 
 // ---------------------------------------------------------------------------------
@@ -514,8 +523,7 @@ struct Smem {
 // domain: no clamping, no boundary faces, every cell active.
 template <typename R, typename S, int STAGE, bool EDGE>
 __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, const int tile,
-                                           const int i0, const int j0, const double t,
-                                           const double dt, const double t_next) {
+                                           const int i0, const int j0) {
   constexpr int TX = Geo<S>::TX, TY = Geo<S>::TY, NT = Geo<S>::NT;
   constexpr int RX = Geo<S>::RX, RB = Geo<S>::RB, VX = Geo<S>::VX, VB = Geo<S>::VB;
   constexpr int NRING = Geo<S>::NRING;
@@ -543,8 +551,10 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   // (VITER per thread), the own cell and the thread's first halo item. Issued one after
   // the other, they cost a memory round trip each.
   const R dT = (sizeof(R) == 4 && p.datum) ? p.datum[tile] : R(0);
-  const R dtr = R(dt);
   const R* __restrict__ src = STAGE == 1 ? p.uin : p.ui;
+  const StepLoads sl = step_loads(p);  // in flight with the tile's loads below
+  double t, dt, t_next, dt_cfl;        // the step's times, formed once those are issued
+  R dtr;
   constexpr int VITER = (VB + NT - 1) / NT;
   constexpr int NHALO = 2 * NRING + 4;  // halo items: first ring, second ring, corners
   // vertex (iv, jv) sits at box position (iv - i0 + 2, jv - j0 + 2); a clamped halo
@@ -658,6 +668,36 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   if (has_item) {
     halo_item(tid, ha, hbb, hnp, hxd);
     load_raw(cell_of(ha, hbb), vb, nmb);
+  }
+  // the step's time and time step (the same in every block), read only now, with the
+  // tile's loads already in flight
+  step_time(p, sl, t, dt, t_next, dt_cfl);
+  dtr = R(dt);
+  if (!(dt > 0.0)) {  // the run has reached t_end: carry the state over unchanged
+    if (STAGE == 1) {
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) (p.vbuf + q * n)[ck] = va[q];  // U^n as loaded
+      }
+      if (tile == 0 && tid == 0) {
+        Ctrl* c = p.ctrl;
+        const int a = p.parity, o = 1 - p.parity;
+        c->t[o] = c->t[a];
+        c->step[o] = c->step[a];
+        for (int q = 0; q < NSLOT; ++q) c->dtc[o].s[q * SLOT_STRIDE] = c->dtc[a].s[q * SLOT_STRIDE];
+        c->dt_used[a] = 0.0;
+      }
+    }
+    return;
+  }
+  if (STAGE == 1 && tile == 0 && tid == 0) {
+    Ctrl* c = p.ctrl;
+    const int a = p.parity, o = 1 - p.parity;
+    c->t[o] = t_next;
+    c->step[o] = c->step[a] + 1;
+    cand_clear(c->dtc[o]);
+    c->dt_used[a] = dt;
+    if (dt_cfl < 1e-12) atomicOr(&c->health, 2);
   }
 #pragma unroll
   for (int k = 0; k < VITER; ++k)
@@ -1082,47 +1122,14 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
 template <typename R, typename S, int STAGE>
 __device__ __forceinline__ void stage_tile(const Params<R> p, const int tile) {
   constexpr int TX = Geo<S>::TX, TY = Geo<S>::TY;
-  const int tid = threadIdx.x;
   const int i0 = (tile % p.tiles_x) * TX, j0 = (tile / p.tiles_x) * TY;
-  const long long n = p.n;
-
-  double t, dt, t_next, dt_cfl;
-  step_time(p, t, dt, t_next, dt_cfl);
-
-  if (!(dt > 0.0)) {  // the run has reached t_end: carry the state over unchanged
-    if (STAGE == 1) {
-      const int ci = i0 + tid % TX, cj = j0 + tid / TX;
-      if (ci < p.nx && cj < p.ny) {
-        const unsigned ck = (unsigned)(cj * p.nx + ci);
-        for (int q = 0; q < 9; ++q) (p.vbuf + q * n)[ck] = (p.uin + q * n)[ck];
-      }
-      if (tile == 0 && tid == 0) {
-        Ctrl* c = p.ctrl;
-        const int a = p.parity, o = 1 - p.parity;
-        c->t[o] = c->t[a];
-        c->step[o] = c->step[a];
-        for (int q = 0; q < NSLOT; ++q) c->dtc[o].s[q * SLOT_STRIDE] = c->dtc[a].s[q * SLOT_STRIDE];
-        c->dt_used[a] = 0.0;
-      }
-    }
-    return;
-  }
-  if (STAGE == 1 && tile == 0 && tid == 0) {
-    Ctrl* c = p.ctrl;
-    const int a = p.parity, o = 1 - p.parity;
-    c->t[o] = t_next;
-    c->step[o] = c->step[a] + 1;
-    cand_clear(c->dtc[o]);
-    c->dt_used[a] = dt;
-    if (dt_cfl < 1e-12) atomicOr(&c->health, 2);
-  }
 
   __shared__ Smem<R, S> sm;
   const bool interior = i0 >= 2 && j0 >= 2 && i0 + TX + 2 <= p.nx && j0 + TY + 2 <= p.ny;
   if (interior)
-    stage_body<R, S, STAGE, false>(p, sm, tile, i0, j0, t, dt, t_next);
+    stage_body<R, S, STAGE, false>(p, sm, tile, i0, j0);
   else
-    stage_body<R, S, STAGE, true>(p, sm, tile, i0, j0, t, dt, t_next);
+    stage_body<R, S, STAGE, true>(p, sm, tile, i0, j0);
 }
 
 // one context: one block per tile, blocks of an XCD on a contiguous band of tiles
