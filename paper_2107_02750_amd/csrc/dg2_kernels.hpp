@@ -221,9 +221,18 @@ __device__ __forceinline__ double uniform(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+__device__ __forceinline__ long long uniform(long long x) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)x), hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+  return ((long long)hi << 32) | (unsigned)lo;
+}
+
 // the step's time step, identical in every block of both stage launches, in two parts
 // so that a kernel can put its own loads between them: the loads (the step's start
 // time; lane k < NSLOT one CFL slot), then the arithmetic
+// s_waitcnt operand for gfx9-family encodings: vmcnt 0 (bits 3:0 and 15:14), expcnt and
+// lgkmcnt left at their maxima (no wait on them)
+constexpr int kWaitVmem = 0x0F70;
+
 struct StepLoads {
   double t, slot;
 };
@@ -1217,8 +1226,7 @@ __device__ __forceinline__ void fv1_side(R h, R zb, R zs, R& hs, R& zss) {
 // domain: no clamping, no boundary faces.
 template <typename R, typename S, bool EDGE>
 __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, const int tile, const int i0,
-                                         const int j0, const double t, const double dt, const long long k,
-                                         const double t_next) {
+                                         const int j0) {
   using SM = SmemFV1<R, S>;
   constexpr int TX = SM::TX, TY = SM::TY, NT = SM::NT, RX = SM::RX;
   constexpr int NRING = 2 * (TX + TY);
@@ -1232,49 +1240,112 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
   const R* __restrict__ hin = p.uin;
   const R* __restrict__ qxin = p.uin + 3 * n;
   const R* __restrict__ qyin = p.uin + 6 * n;
-  const R dtr = R(dt);
   const R ht = p.h_tol, g = p.g;
   const R dT = tile_datum(p, i0, j0);
 
-  // ---- phase 1: the box depths and velocities (friction applied) and bed means ----
-  // returns the cell's discharges after friction
-  auto load = [&](int ab, int bb, R& qx, R& qy) {  // box position (ab, bb)
+  // No vector memory operation is in flight when a tile body starts; the wait costs
+  // nothing and keeps the wait-count analysis from carrying in the other body's loads.
+  __builtin_amdgcn_s_waitcnt(kWaitVmem);
+
+  // ---- phase 1: the step's time step; the box depths and velocities (friction
+  // applied) and bed means ----
+  // The step count and time, then the state, Manning coefficient and bed vertices of the
+  // own cell and of the thread's halo item are all issued before any is waited on; the
+  // ring candidate, whose slot the count picks, follows while they are in flight. (The
+  // other two rings are not read: one takes this step's atomic minima, the other is
+  // being cleared, and reading them costs more than the extra round trip.)
+  const int a = p.parity, o = 1 - p.parity;
+  const long long k_ld = ctl->step[a];
+  const double t_ld = ctl->t[a];
+  struct Raw {
+    R h, qx, qy, nm, sw, se, nw, ne;
+  };
+  auto load_raw = [&](int ab, int bb, Raw& w) {  // box position (ab, bb)
     int i = i0 - 1 + ab, j = j0 - 1 + bb;
     if (EDGE) {
       i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
       j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
     }
     const unsigned kk = (unsigned)(j * nx + i);
-    const R h = hin[kk];
-    qx = qxin[kk];
-    qy = qyin[kk];
-    const R nm = p.manning ? p.manning[kk] : p.n_scalar;
-    if (nm > R(0)) {
+    w.h = hin[kk];
+    w.qx = qxin[kk];
+    w.qy = qyin[kk];
+    w.nm = p.manning ? p.manning[kk] : p.n_scalar;
+    w.sw = zvat(p, i, j, dT);
+    w.se = zvat(p, i + 1, j, dT);
+    w.nw = zvat(p, i, j + 1, dT);
+    w.ne = zvat(p, i + 1, j + 1, dT);
+  };
+  const int ca = tid % TX + 1, cb = tid / TX + 1, cpos = cb * RX + ca;
+  Raw w0, w1;
+  load_raw(ca, cb, w0);
+  int hab = 0, hbb = 0;
+  const bool has_item = tid < NRING;
+  if (has_item) {
+    if (tid < TY) { hab = 0; hbb = tid + 1; }
+    else if (tid < 2 * TY) { hab = TX + 1; hbb = tid - TY + 1; }
+    else if (tid < 2 * TY + TX) { hab = tid - 2 * TY + 1; hbb = 0; }
+    else { hab = tid - 2 * TY - TX + 1; hbb = TY + 1; }
+    load_raw(hab, hbb, w1);
+  }
+
+  // the step's time step from the ring slot of this step
+  const long long k = uniform(k_ld);
+  const double t = uniform(t_ld);
+  const double mm = cand_read(ctl->dtr[k % 3]);
+  double dt = (mm == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * mm;
+  const double dt_cfl = dt;
+  if (p.dt_max > 0.0 && p.dt_max < dt) dt = p.dt_max;
+  double t_next = t + dt;
+  if (p.t_end - t <= dt) {
+    dt = p.t_end - t;
+    t_next = p.t_end;
+  }
+  if (!(dt > 0.0)) {  // past t_end: carry the state over
+    if (active) {
+      p.vbuf[ck] = w0.h;
+      (p.vbuf + 3 * n)[ck] = w0.qx;
+      (p.vbuf + 6 * n)[ck] = w0.qy;
+    }
+    if (tile == 0 && tid == 0) {
+      ctl->t[o] = t;
+      ctl->step[o] = k;
+      ctl->dt_used[a] = 0.0;
+    }
+    return;
+  }
+  if (tile == 0 && tid == 0) {
+    ctl->t[o] = t_next;
+    ctl->step[o] = k + 1;
+    ctl->dt_used[a] = dt;
+    cand_clear(ctl->dtr[(k + 2) % 3]);
+    if (dt_cfl < 1e-12) atomicOr(&ctl->health, 2);
+  }
+  const R dtr = R(dt);
+
+  // friction, then the box cell's depth, velocities and bed mean (eq 8, diagonal pairs)
+  // to LDS; returns the cell's discharges after friction
+  auto publish = [&](int ab, int bb, const Raw& w, R& qx, R& qy) {
+    qx = w.qx;
+    qy = w.qy;
+    if (w.nm > R(0)) {
       R dqx, dqy;
-      friction_inc(p.g * nm * nm * dtr, ht, h, qx, qy, dqx, dqy);
+      friction_inc(g * w.nm * w.nm * dtr, ht, w.h, qx, qy, dqx, dqy);
       qx += dqx;
       qy += dqy;
     }
-    const R sw = zvat(p, i, j, dT), se = zvat(p, i + 1, j, dT);
-    const R nw = zvat(p, i, j + 1, dT), ne = zvat(p, i + 1, j + 1, dT);
     const int r = bb * RX + ab;
-    const R rr = frcp(fmaxr(h, Tiny<R>::v));
-    sm.h[r] = h;
-    sm.u[r] = h > ht ? qx * rr : R(0);
-    sm.v[r] = h > ht ? qy * rr : R(0);
-    sm.z0[r] = R(0.25) * ((ne + sw) + (nw + se));  // eq 8, diagonal pairs
+    const R rr = frcp(fmaxr(w.h, Tiny<R>::v));
+    sm.h[r] = w.h;
+    sm.u[r] = w.h > ht ? qx * rr : R(0);
+    sm.v[r] = w.h > ht ? qy * rr : R(0);
+    sm.z0[r] = R(0.25) * ((w.ne + w.sw) + (w.nw + w.se));
   };
-  const int ca = tid % TX + 1, cb = tid / TX + 1, cpos = cb * RX + ca;
   R qx0, qy0;
-  load(ca, cb, qx0, qy0);
-  if (tid < NRING) {
-    int ab, bb;
-    if (tid < TY) { ab = 0; bb = tid + 1; }
-    else if (tid < 2 * TY) { ab = TX + 1; bb = tid - TY + 1; }
-    else if (tid < 2 * TY + TX) { ab = tid - 2 * TY + 1; bb = 0; }
-    else { ab = tid - 2 * TY - TX + 1; bb = TY + 1; }
+  publish(ca, cb, w0, qx0, qy0);
+  if (has_item) {
     R qxr, qyr;
-    load(ab, bb, qxr, qyr);
+    publish(hab, hbb, w1, qxr, qyr);
   }
   __syncthreads();
 
@@ -1417,52 +1488,13 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
   const int b = blockIdx.x;
   const int tile = (b % NXCD) * p.per_xcd + b / NXCD;
   if (tile >= p.n_tiles) return;
-  const int tid = threadIdx.x;
   const int nx = p.nx, ny = p.ny;
-  const long long n = p.n;
   const int i0 = (tile % p.tiles_x) * TX, j0 = (tile / p.tiles_x) * TY;
-
-  // the step's time step from the ring slot of this step
-  Ctrl* ctl = p.ctrl;
-  const int a = p.parity, o = 1 - p.parity;
-  const long long k = ctl->step[a];
-  const double t = uniform(ctl->t[a]);
-  const double mm = cand_read(ctl->dtr[k % 3]);
-  double dt = (mm == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * mm;
-  const double dt_cfl = dt;
-  if (p.dt_max > 0.0 && p.dt_max < dt) dt = p.dt_max;
-  double t_next = t + dt;
-  if (p.t_end - t <= dt) {
-    dt = p.t_end - t;
-    t_next = p.t_end;
-  }
-  if (!(dt > 0.0)) {  // past t_end: carry the state over
-    const int ci = i0 + tid % TX, cj = j0 + tid / TX;
-    if (ci < nx && cj < ny) {
-      const unsigned ck = (unsigned)(cj * nx + ci);
-      (p.vbuf)[ck] = p.uin[ck];
-      (p.vbuf + 3 * n)[ck] = p.uin[3 * n + ck];
-      (p.vbuf + 6 * n)[ck] = p.uin[6 * n + ck];
-    }
-    if (tile == 0 && tid == 0) {
-      ctl->t[o] = t;
-      ctl->step[o] = k;
-      ctl->dt_used[a] = 0.0;
-    }
-    return;
-  }
-  if (tile == 0 && tid == 0) {
-    ctl->t[o] = t_next;
-    ctl->step[o] = k + 1;
-    ctl->dt_used[a] = dt;
-    cand_clear(ctl->dtr[(k + 2) % 3]);
-    if (dt_cfl < 1e-12) atomicOr(&ctl->health, 2);
-  }
   const bool interior = i0 >= 1 && j0 >= 1 && i0 + TX + 1 <= nx && j0 + TY + 1 <= ny;
   if (interior)
-    fv1_body<R, S, false>(p, sm, tile, i0, j0, t, dt, k, t_next);
+    fv1_body<R, S, false>(p, sm, tile, i0, j0);
   else
-    fv1_body<R, S, true>(p, sm, tile, i0, j0, t, dt, k, t_next);
+    fv1_body<R, S, true>(p, sm, tile, i0, j0);
 }
 
 // ---------------------------------------------------------------------------------
