@@ -249,14 +249,146 @@ struct AdjArgs {
 };
 
 // the adjoint works on 32 x 8 tiles: the stage input and mu of the tile and a one-cell
-// halo are staged in LDS, so the neighbour reads of the face terms are LDS reads
+// halo are staged in LDS, so the neighbour reads of the face terms are LDS reads; once
+// every face is done, the same LDS holds each face's cotangents of its two face limits
 constexpr int ADJ_TX = 32, ADJ_TY = 8, ADJ_RX = ADJ_TX + 2, ADJ_RB = ADJ_RX * (ADJ_TY + 2);
-struct AdjSmem {
-  double v[9][ADJ_RB];  // stage input V
-  double m[9][ADJ_RB];  // mu = alpha lam
+constexpr int ADJ_NFX = (ADJ_TX + 1) * ADJ_TY, ADJ_NFY = ADJ_TX * (ADJ_TY + 1);
+union AdjSmem {
+  struct {
+    double v[9][ADJ_RB];  // stage input V
+    double m[9][ADJ_RB];  // mu = alpha lam
+  };
+  struct {                // per face: (h, qx, qy) cotangents of the low cell's limit (0..2)
+    double fx[6][ADJ_NFX];  // and of the high cell's (3..5); x face f of tile row b at
+    double fy[6][ADJ_NFY];  // b * (TX + 1) + f, y face f of tile column a at f * TX + a
+  };
 };
 
-__global__ __launch_bounds__(ADJ_TX * ADJ_TY) void adj_stage_kernel(Params<double> p, AdjArgs a) {
+// One face of the adjoint: the cotangent of the face's stored flux (from mu of the cells
+// on both sides) goes back through the HLL flux, the ghost state (boundary faces) and
+// the revision to the face limits (h, qx, qy) of the cells on both sides: lo for the
+// low cell (its high limit), hi for the high cell (its low limit). A boundary face has
+// one cell; the ghost's cotangent is folded into it.
+struct AdjFace {
+  bool xdir;
+  int posL, posR;     // box positions of the low and high cells
+  bool realL, realR;  // in the domain (at most one is not: a boundary face)
+  int va, vb;         // the face's first bed vertex
+  int line;           // row (x face) or column (y face) of the face
+};
+
+__device__ __forceinline__ void adj_face(const Params<double>& p, const AdjArgs& a, const AdjSmem& sm,
+                                         const AdjFace& F, double lo[3], double hi[3], int& bad) {
+  const int nx = p.nx, ny = p.ny;
+  const double g = p.g, ht = p.h_tol, s3 = K<double>::s3;
+  const double idx = 1.0 / p.dx, cc = -s3 * idx;
+  const double slack = dsqrt(p.gd * p.htd);
+  const bool xdir = F.xdir;
+  auto V = [&](int pos, int q) { return sm.v[q][pos]; };
+  auto mu = [&](int pos, int q) { return sm.m[q][pos]; };
+  auto zvv = [&](int iv, int jv) { return p.zv[(long long)jv * (nx + 1) + iv]; };
+  auto umean = [&](int pos, bool xv) {
+    const double h0 = V(pos, 0);
+    return h0 > ht ? V(pos, xv ? 3 : 6) * frcp(h0) : 0.0;
+  };
+  const double zf = 0.5 * (zvv(F.va, F.vb) + (xdir ? zvv(F.va, F.vb + 1) : zvv(F.va + 1, F.vb)));
+  // velocity caps: the larger mean-velocity magnitude of the face's cells plus the slack
+  const int pL = F.realL ? F.posL : F.posR, pR = F.realR ? F.posR : F.posL;
+  const double ucap = fmax(fabs(umean(pL, true)), fabs(umean(pR, true))) + slack;
+  const double vcap_ = fmax(fabs(umean(pL, false)), fabs(umean(pR, false))) + slack;
+  // a cell's face limit (sgn +1: its high side, -1: its low side) after the revision
+  // (both sides share the face bed in this regime)
+  double uL = 0.0, vL = 0.0, rL = 0.0, uR = 0.0, vR = 0.0, rR = 0.0;
+  NSide sL{}, sR{};
+  auto side = [&](int pos, double sgn, double& u, double& v, double& r) {
+    const double c1 = xdir ? V(pos, 1) : V(pos, 2), c4 = xdir ? V(pos, 4) : V(pos, 5);
+    const double c7 = xdir ? V(pos, 7) : V(pos, 8);
+    const double h = V(pos, 0) + sgn * s3 * c1, qx = V(pos, 3) + sgn * s3 * c4, qy = V(pos, 6) + sgn * s3 * c7;
+    r = frcp(h);
+    const double hs = fmax0((h + zf) - zf);
+    u = qx * r;
+    v = qy * r;
+    if (!(h > ht) || !(hs > 0.0)) bad |= 1;
+    if (fabs(u) > ucap || fabs(v) > vcap_) bad |= 2;
+    return NSide{hs, xdir ? u : v, xdir ? v : u};
+  };
+  if (F.realL) sL = side(F.posL, 1.0, uL, vL, rL);
+  if (F.realR) sR = side(F.posR, -1.0, uR, vR, rR);
+  // the ghost beyond a boundary face, from the cell's side in the normal frame
+  int kind = -1, qslot = -1;
+  double qn = 0.0, hc = 0.0, inward = 0.0, width = 1.0;
+  if (!F.realL || !F.realR) {
+    const bool high = !F.realR;  // the cell is the low one: an east or north boundary
+    const NSide own = high ? sL : sR;
+    const int code = xdir ? p.bface[(high ? ny : 0) + F.line] : p.bface[2 * ny + (high ? nx : 0) + F.line];
+    kind = code & 255;
+    inward = high ? -1.0 : 1.0;
+    NSide nb = own;
+    if (kind == 1) {
+      nb.un = -own.un;
+    } else if (kind == 2) {
+      const Seg& sg = p.segs[(code >> 8) - 1];
+      nb = NSide{sg.h_b, xdir ? sg.u_b : sg.v_b, xdir ? sg.v_b : sg.u_b};
+    } else if (kind == 3) {
+      const Seg& sg = p.segs[(code >> 8) - 1];
+      qslot = xdir ? (high ? ny : 0) + F.line : 2 * ny + (high ? nx : 0) + F.line;
+      width = sg.width;
+      qn = hydrograph(sg, p.knots, p.knots + p.max_knots, a.t) / width;
+      hc = dcbrt(qn * qn / g);
+      const double hg = own.h > hc ? own.h : hc;
+      nb = NSide{hg, hg > 0.0 ? inward * (qn / hg) : 0.0, 0.0};
+    }
+    if (high) sR = nb;
+    else sL = nb;
+  }
+  // cotangent of each stored flux component [mass, x-mom, y-mom]: L0 of the low cell
+  // gets -F/dx and of the high cell +F/dx, L1 (this direction) of both cc F
+  double mt[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const double tL = F.realL ? -idx * mu(F.posL, 3 * m) + cc * (xdir ? mu(F.posL, 3 * m + 1) : mu(F.posL, 3 * m + 2)) : 0.0;
+    const double tR = F.realR ? idx * mu(F.posR, 3 * m) + cc * (xdir ? mu(F.posR, 3 * m + 1) : mu(F.posR, 3 * m + 2)) : 0.0;
+    mt[m] = tL + tR;
+  }
+  // in the normal frame: [mass, normal momentum, tangential momentum]
+  const double fb[3] = {mt[0], xdir ? mt[1] : mt[2], xdir ? mt[2] : mt[1]};
+  NSide Lb, Rb;
+  hll_rev(g, sL, sR, fb, Lb, Rb);
+  if (kind >= 0) {
+    const bool high = !F.realR;
+    NSide& ob = high ? Lb : Rb;        // the cell's cotangent
+    const NSide gb = high ? Rb : Lb;   // the ghost's (it depends on the cell's side)
+    if (kind == 0) {                   // transmissive: a copy
+      ob.h += gb.h; ob.un += gb.un; ob.ut += gb.ut;
+    } else if (kind == 1) {            // wall: the normal velocity reversed
+      ob.h += gb.h; ob.un -= gb.un; ob.ut += gb.ut;
+    } else if (kind == 3) {            // critical-depth inflow: depends on h and Q
+      const NSide own = high ? sL : sR;
+      const double hg = own.h > hc ? own.h : hc;
+      double hgb = gb.h, qnb = 0.0;
+      if (hg > 0.0) {
+        const double r = frcp(hg);
+        qnb += gb.un * inward * r;
+        hgb -= gb.un * inward * qn * r * r;
+      }
+      if (own.h > hc) ob.h += hgb;
+      else if (hc > 0.0 && qn != 0.0) qnb += hgb * 2.0 * hc / (3.0 * qn);  // hc = (qn^2 / g)^(1/3)
+      a.gqf[qslot] = qnb / width;
+    }
+  }
+  // back through the revision of each cell's side: u = qx / h, v = qy / h, h* = h
+  auto back = [&](const NSide& ob, double u, double v, double r, double o[3]) {
+    const double ub = xdir ? ob.un : ob.ut, vbk = xdir ? ob.ut : ob.un;
+    o[0] = ob.h - (ub * u + vbk * v) * r;
+    o[1] = ub * r;
+    o[2] = vbk * r;
+  };
+  lo[0] = lo[1] = lo[2] = hi[0] = hi[1] = hi[2] = 0.0;
+  if (F.realL) back(Lb, uL, vL, rL, lo);
+  if (F.realR) back(Rb, uR, vR, rR, hi);
+}
+
+__global__ __launch_bounds__(ADJ_TX * ADJ_TY, 3) void adj_stage_kernel(Params<double> p, AdjArgs a) {
   __shared__ AdjSmem sm;
   const long long n = p.n;
   const int nx = p.nx, ny = p.ny;
@@ -275,134 +407,150 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY) void adj_stage_kernel(Params<doubl
     }
   }
   __syncthreads();
-  const int i = i0 + tid % ADJ_TX, j = j0 + tid / ADJ_TX;
-  if (i >= nx || j >= ny) return;  // no barrier follows
+  const int ta = tid % ADJ_TX, tb = tid / ADJ_TX;
+  const int i = i0 + ta, j = j0 + tb;
+  const bool active = i < nx && j < ny;
+  const int iend = nx < i0 + ADJ_TX ? nx : i0 + ADJ_TX, jend = ny < j0 + ADJ_TY ? ny : j0 + ADJ_TY;
   const long long c = (long long)j * nx + i;
-  const int cpos = (tid / ADJ_TX + 1) * ADJ_RX + tid % ADJ_TX + 1;
+  const int cpos = (tb + 1) * ADJ_RX + ta + 1;
   const double g = p.g, ht = p.h_tol, s3 = K<double>::s3;
   const double idx = 1.0 / p.dx, cc = -s3 * idx, i2s3 = K<double>::inv_2s3;
   const double k2s3 = 2.0 * s3 * g * idx;
-  const double slack = dsqrt(p.gd * p.htd);
-  // box position of a cell: the cell itself or one of its four neighbours
-  auto V = [&](int pos, int q) { return sm.v[q][pos]; };
-  auto mu = [&](int pos, int q) { return sm.m[q][pos]; };
   auto zvv = [&](int iv, int jv) { return p.zv[(long long)jv * (nx + 1) + iv]; };
-  auto umean = [&](int pos, bool xv) {
-    const double h0 = V(pos, 0);
-    return h0 > ht ? V(pos, xv ? 3 : 6) * frcp(h0) : 0.0;
-  };
-  // the cell's own coefficients, cotangents and mean velocities, read once
-  double vc[9], mc[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    vc[q] = V(cpos, q);
-    mc[q] = mu(cpos, q);
-  }
-  const double u0c = vc[0] > ht ? vc[3] * frcp(vc[0]) : 0.0;
-  const double v0c = vc[0] > ht ? vc[6] * frcp(vc[0]) : 0.0;
   int bad = 0;
-  if (!(vc[0] > ht)) bad |= 1;
+
+  // local terms of the cell's own L (Gauss fluxes and bed source), per direction:
+  // mu . L_local = -cc (mu_d gs0 + mu_{3+d} gs1 + mu_{6+d} gs2) - mu_qn0 s0 - mu_qn1 s1
+  double nl[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) nl[q] = 0.0;
+  if (active) {
+    double vc[9], mc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      vc[q] = sm.v[q][cpos];
+      mc[q] = sm.m[q][cpos];
+    }
+    if (!(vc[0] > ht)) bad |= 1;
+#pragma unroll 1
+    for (int dir = 0; dir < 2; ++dir) {
+      const bool xdir = dir == 0;
+      const double c1 = xdir ? vc[1] : vc[2], c4 = xdir ? vc[4] : vc[5], c7 = xdir ? vc[7] : vc[8];
+      const double hH = vc[0] + s3 * c1, qxH = vc[3] + s3 * c4, qyH = vc[6] + s3 * c7;
+      const double hL = vc[0] - s3 * c1, qxL = vc[3] - s3 * c4, qyL = vc[6] - s3 * c7;
+      double zH, zL;
+      if (xdir) { zH = 0.5 * (zvv(i + 1, j + 1) + zvv(i + 1, j)); zL = 0.5 * (zvv(i, j + 1) + zvv(i, j)); }
+      else { zH = 0.5 * (zvv(i, j + 1) + zvv(i + 1, j + 1)); zL = 0.5 * (zvv(i, j) + zvv(i + 1, j)); }
+      // revised sides (the bed of each side is its own face bed)
+      const double rH = frcp(hH), rL = frcp(hL);
+      const double shH = fmax0((hH + zH) - zH), shL = fmax0((hL + zL) - zL);
+      const double uH = qxH * rH, vH = qyH * rH, uL = qxL * rL, vL = qyL * rL;
+      const double zb1 = (fminr(hH + zH, zH) - fminr(hL + zL, zL)) * i2s3;
+      const double hb0 = 0.5 * (shH + shL), hb1 = (shH - shL) * i2s3;
+      const double qxH2 = shH * uH, qxL2 = shL * uL, qyH2 = shH * vH, qyL2 = shL * vL;
+      const double qb0 = 0.5 * (qxH2 + qxL2), qb1 = (qxH2 - qxL2) * i2s3;
+      const double rb0 = 0.5 * (qyH2 + qyL2), rb1 = (qyH2 - qyL2) * i2s3;
+      // cotangents of the stored Gauss sums and of the source terms
+      const double gsb[3] = {-cc * (xdir ? mc[1] : mc[2]), -cc * (xdir ? mc[4] : mc[5]),
+                             -cc * (xdir ? mc[7] : mc[8])};
+      const double s0b = -(xdir ? mc[3] : mc[6]), s1b = -(xdir ? mc[4] : mc[8]);
+      // Gauss flux cotangents in the normal frame (y faces: normal momentum is y)
+      const double fbn[3] = {gsb[0], xdir ? gsb[1] : gsb[2], xdir ? gsb[2] : gsb[1]};
+      const double qn0 = xdir ? qb0 : rb0, qn1 = xdir ? qb1 : rb1, qt0 = xdir ? rb0 : qb0, qt1 = xdir ? rb1 : qb1;
+      double hpb, qnpb, qtpb, hmb, qnmb, qtmb;
+      gauss_rev(g, ht, hb0 + hb1, qn0 + qn1, qt0 + qt1, fbn, hpb, qnpb, qtpb);
+      gauss_rev(g, ht, hb0 - hb1, qn0 - qn1, qt0 - qt1, fbn, hmb, qnmb, qtmb);
+      // s0 = k2s3 hb0 zb1, s1 = k2s3 hb1 zb1 (zb1 does not depend on the coefficients here)
+      const double hb0b = hpb + hmb + s0b * k2s3 * zb1, hb1b = hpb - hmb + s1b * k2s3 * zb1;
+      const double qn0b = qnpb + qnmb, qn1b = qnpb - qnmb, qt0b = qtpb + qtmb, qt1b = qtpb - qtmb;
+      const double qb0b = xdir ? qn0b : qt0b, qb1b = xdir ? qn1b : qt1b;
+      const double rb0b = xdir ? qt0b : qn0b, rb1b = xdir ? qt1b : qn1b;
+      const double qxH2b = 0.5 * qb0b + i2s3 * qb1b, qxL2b = 0.5 * qb0b - i2s3 * qb1b;
+      const double qyH2b = 0.5 * rb0b + i2s3 * rb1b, qyL2b = 0.5 * rb0b - i2s3 * rb1b;
+      const double shHb = 0.5 * hb0b + i2s3 * hb1b + qxH2b * uH + qyH2b * vH;
+      const double shLb = 0.5 * hb0b - i2s3 * hb1b + qxL2b * uL + qyL2b * vL;
+      const double uHb = qxH2b * shH, vHb = qyH2b * shH, uLb = qxL2b * shL, vLb = qyL2b * shL;
+      // through the revision of each side
+      const double hHb = shHb - (uHb * uH + vHb * vH) * rH, qxHb = uHb * rH, qyHb = vHb * rH;
+      const double hLb = shLb - (uLb * uL + vLb * vL) * rL, qxLb = uLb * rL, qyLb = vLb * rL;
+      // high side: d/dU0 = 1, d/dU1d = sqrt(3); low side: 1, -sqrt(3)
+      nl[0] += hHb + hLb;
+      nl[3] += qxHb + qxLb;
+      nl[6] += qyHb + qyLb;
+      nl[1] += xdir ? s3 * (hHb - hLb) : 0.0;
+      nl[4] += xdir ? s3 * (qxHb - qxLb) : 0.0;
+      nl[7] += xdir ? s3 * (qyHb - qyLb) : 0.0;
+      nl[2] += xdir ? 0.0 : s3 * (hHb - hLb);
+      nl[5] += xdir ? 0.0 : s3 * (qxHb - qxLb);
+      nl[8] += xdir ? 0.0 : s3 * (qyHb - qyLb);
+    }
+  }
+
+  // every face once: each cell's west and south faces, and (threads 0..TY+TX-1) the east
+  // faces of the tile's last column and the north faces of its last row
+  double ow[6], os[6], oe[6];
+  if (active) {
+    const AdjFace fw{true, cpos - 1, cpos, i > 0, true, i, j, j};
+    adj_face(p, a, sm, fw, ow, ow + 3, bad);
+    const AdjFace fs{false, cpos - ADJ_RX, cpos, j > 0, true, i, j, i};
+    adj_face(p, a, sm, fs, os, os + 3, bad);
+  }
+  int eslot = -1;  // 0..NFX-1: an x face, NFX + ...: a y face
+  if (tid < ADJ_TY) {
+    const int jr = j0 + tid;
+    if (jr < ny) {
+      const int pos = (tid + 1) * ADJ_RX + (iend - i0);  // the low cell, column iend - 1
+      const AdjFace fe{true, pos, pos + 1, true, iend < nx, iend, jr, jr};
+      adj_face(p, a, sm, fe, oe, oe + 3, bad);
+      eslot = tid * (ADJ_TX + 1) + (iend - i0);
+    }
+  } else if (tid < ADJ_TY + ADJ_TX) {
+    const int ic = i0 + tid - ADJ_TY;
+    if (ic < nx) {
+      const int pos = (jend - j0) * ADJ_RX + (ic - i0) + 1;  // the low cell, row jend - 1
+      const AdjFace fn{false, pos, pos + ADJ_RX, true, jend < ny, ic, jend, ic};
+      adj_face(p, a, sm, fn, oe, oe + 3, bad);
+      eslot = ADJ_NFX + (jend - j0) * ADJ_TX + (ic - i0);
+    }
+  }
+  __syncthreads();  // the box is no longer read: its LDS takes the face cotangents
+  if (active) {
+    const int xr = tb * (ADJ_TX + 1) + ta, yr = tb * ADJ_TX + ta;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      sm.fx[q][xr] = ow[q];
+      sm.fy[q][yr] = os[q];
+    }
+  }
+  if (eslot >= 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      if (eslot < ADJ_NFX) sm.fx[q][eslot] = oe[q];
+      else sm.fy[q][eslot - ADJ_NFX] = oe[q];
+    }
+  }
+  __syncthreads();
+  if (!active) return;  // no barrier follows
+
+  // the cell's face-limit cotangents (W, E, S, N), chained to the coefficients as
+  // d/dU0 = 1, d/dU1 = sgn sqrt(3) (sgn + for the high side of the cell)
   double nu[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) nu[q] = 0.0;
-
-  // the four faces: 0 W, 1 E, 2 S, 3 N; sgn = side of the cell's limit (+ for E/N).
-  // The cotangent of a face's flux (from both cells sharing it) goes back through the
-  // HLL flux, the ghost state (boundary faces) and the revision to the cell's own face
-  // limit (h, qx, qy), which chains to the coefficients as d/dU0 = 1, d/dU1 = sgn sqrt(3)
-#pragma unroll 1
-  for (int f = 0; f < 4; ++f) {
-    const bool xdir = f < 2;
-    const bool high = (f & 1) != 0;
-    const double sgn = high ? 1.0 : -1.0;
-    const double c1 = xdir ? vc[1] : vc[2], c4 = xdir ? vc[4] : vc[5], c7 = xdir ? vc[7] : vc[8];
-    const double ho = vc[0] + sgn * s3 * c1, qxo = vc[3] + sgn * s3 * c4, qyo = vc[6] + sgn * s3 * c7;
-    // face bed (vertex mean) and the neighbour across the face
-    const int ni = xdir ? (high ? i + 1 : i - 1) : i, nj = xdir ? j : (high ? j + 1 : j - 1);
-    const int va = xdir ? (high ? i + 1 : i) : i, vb = xdir ? j : (high ? j + 1 : j);  // first vertex
-    const double zf = 0.5 * (zvv(va, vb) + (xdir ? zvv(va, vb + 1) : zvv(va + 1, vb)));
-    const bool inside = ni >= 0 && ni < nx && nj >= 0 && nj < ny;
-    const int nk = inside ? cpos + (xdir ? (high ? 1 : -1) : (high ? ADJ_RX : -ADJ_RX)) : cpos;
-    // own side after the revision (both sides share the face bed in this regime)
-    const double ro = frcp(ho);
-    const double hs = fmax0((ho + zf) - zf), uo = qxo * ro, vo = qyo * ro;
-    if (!(ho > ht) || !(hs > 0.0)) bad |= 1;
-    const double ucap = fmax(fabs(u0c), fabs(inside ? umean(nk, true) : u0c)) + slack;
-    const double vcap_ = fmax(fabs(v0c), fabs(inside ? umean(nk, false) : v0c)) + slack;
-    if (fabs(uo) > ucap || fabs(vo) > vcap_) bad |= 2;
-    const NSide own{hs, xdir ? uo : vo, xdir ? vo : uo};
-    NSide nb;
-    int kind = -1, qslot = -1;
-    double qn = 0.0, hc = 0.0, inward = 0.0, width = 1.0;
-    if (inside) {
-      const double ns = -sgn;  // the neighbour's limit on its opposite side
-      const double n1 = xdir ? V(nk, 1) : V(nk, 2), n4 = xdir ? V(nk, 4) : V(nk, 5);
-      const double n7 = xdir ? V(nk, 7) : V(nk, 8);
-      const double hn = V(nk, 0) + ns * s3 * n1, qxn = V(nk, 3) + ns * s3 * n4, qyn = V(nk, 6) + ns * s3 * n7;
-      const double rn = frcp(hn);
-      const double hsn = fmax0((hn + zf) - zf);
-      if (!(hn > ht) || !(hsn > 0.0)) bad |= 1;
-      nb = NSide{hsn, xdir ? qxn * rn : qyn * rn, xdir ? qyn * rn : qxn * rn};
-    } else {
-      // ghost beyond a boundary face, from the own side in the normal frame
-      const int code = xdir ? p.bface[(high ? ny : 0) + j] : p.bface[2 * ny + (high ? nx : 0) + i];
-      kind = code & 255;
-      inward = high ? -1.0 : 1.0;
-      nb = own;
-      if (kind == 1) {
-        nb.un = -own.un;
-      } else if (kind == 2) {
-        const Seg& sg = p.segs[(code >> 8) - 1];
-        nb = NSide{sg.h_b, xdir ? sg.u_b : sg.v_b, xdir ? sg.v_b : sg.u_b};
-      } else if (kind == 3) {
-        const Seg& sg = p.segs[(code >> 8) - 1];
-        qslot = xdir ? (high ? ny : 0) + j : 2 * ny + (high ? nx : 0) + i;
-        width = sg.width;
-        qn = hydrograph(sg, p.knots, p.knots + p.max_knots, a.t) / width;
-        hc = dcbrt(qn * qn / g);
-        const double hg = own.h > hc ? own.h : hc;
-        nb = NSide{hg, hg > 0.0 ? inward * (qn / hg) : 0.0, 0.0};
-      }
-    }
-    // cotangent of each stored flux component [mass, x-mom, y-mom], from both cells:
-    // L0 gets -(F_high - F_low)/dx, L1 (this direction) gets cc (F_high + F_low)
-    double mt[3];
+  const int xr = tb * (ADJ_TX + 1) + ta, yr = tb * ADJ_TX + ta;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      const double own0 = mc[3 * m], own1 = xdir ? mc[3 * m + 1] : mc[3 * m + 2];
-      double v = (high ? -idx : idx) * own0 + cc * own1;
-      if (inside) {
-        const double nb0 = mu(nk, 3 * m), nb1 = xdir ? mu(nk, 3 * m + 1) : mu(nk, 3 * m + 2);
-        v += (high ? idx : -idx) * nb0 + cc * nb1;
-      }
-      mt[m] = v;
+  for (int f = 0; f < 4; ++f) {
+    const bool xdir = f < 2, high = (f & 1) != 0;
+    const double sgn = high ? 1.0 : -1.0;
+    const int o = high ? 0 : 3;  // the cell is the low side of its east and north faces
+    double hb, qxb, qyb;
+    if (xdir) {
+      const int r = xr + (high ? 1 : 0);
+      hb = sm.fx[o][r]; qxb = sm.fx[o + 1][r]; qyb = sm.fx[o + 2][r];
+    } else {
+      const int r = yr + (high ? ADJ_TX : 0);
+      hb = sm.fy[o][r]; qxb = sm.fy[o + 1][r]; qyb = sm.fy[o + 2][r];
     }
-    // in the normal frame: [mass, normal momentum, tangential momentum]
-    const double fb[3] = {mt[0], xdir ? mt[1] : mt[2], xdir ? mt[2] : mt[1]};
-    NSide Lb, Rb;
-    if (high) hll_rev(g, own, nb, fb, Lb, Rb);
-    else hll_rev(g, nb, own, fb, Lb, Rb);
-    NSide ob = high ? Lb : Rb;          // the own side's cotangent
-    const NSide gb = high ? Rb : Lb;    // the other side's (a ghost's depends on the own side)
-    if (kind == 0) {                    // transmissive: a copy
-      ob.h += gb.h; ob.un += gb.un; ob.ut += gb.ut;
-    } else if (kind == 1) {             // wall: the normal velocity reversed
-      ob.h += gb.h; ob.un -= gb.un; ob.ut += gb.ut;
-    } else if (kind == 3) {             // critical-depth inflow: depends on h and Q
-      const double hg = own.h > hc ? own.h : hc;
-      double hgb = gb.h, qnb = 0.0;
-      if (hg > 0.0) {
-        const double r = frcp(hg);
-        qnb += gb.un * inward * r;
-        hgb -= gb.un * inward * qn * r * r;
-      }
-      if (own.h > hc) ob.h += hgb;
-      else if (hc > 0.0 && qn != 0.0) qnb += hgb * 2.0 * hc / (3.0 * qn);  // hc = (qn^2 / g)^(1/3)
-      a.gqf[qslot] = qnb / width;
-    }
-    // back through the revision: u = qx / h, v = qy / h, h* = h
-    const double ub = xdir ? ob.un : ob.ut, vbk = xdir ? ob.ut : ob.un;
-    const double hb = ob.h - (ub * uo + vbk * vo) * ro, qxb = ub * ro, qyb = vbk * ro;
     nu[0] += hb;
     nu[3] += qxb;
     nu[6] += qyb;
@@ -414,64 +562,11 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY) void adj_stage_kernel(Params<doubl
     nu[8] += xdir ? 0.0 : sgn * s3 * qyb;
   }
 
-  // local terms of the cell's own L (Gauss fluxes and bed source), per direction:
-  // mu . L_local = -cc (mu_d gs0 + mu_{3+d} gs1 + mu_{6+d} gs2) - mu_qn0 s0 - mu_qn1 s1
-#pragma unroll 1
-  for (int dir = 0; dir < 2; ++dir) {
-    const bool xdir = dir == 0;
-    const double c1 = xdir ? vc[1] : vc[2], c4 = xdir ? vc[4] : vc[5], c7 = xdir ? vc[7] : vc[8];
-    const double hH = vc[0] + s3 * c1, qxH = vc[3] + s3 * c4, qyH = vc[6] + s3 * c7;
-    const double hL = vc[0] - s3 * c1, qxL = vc[3] - s3 * c4, qyL = vc[6] - s3 * c7;
-    double zH, zL;
-    if (xdir) { zH = 0.5 * (zvv(i + 1, j + 1) + zvv(i + 1, j)); zL = 0.5 * (zvv(i, j + 1) + zvv(i, j)); }
-    else { zH = 0.5 * (zvv(i, j + 1) + zvv(i + 1, j + 1)); zL = 0.5 * (zvv(i, j) + zvv(i + 1, j)); }
-    // revised sides (the bed of each side is its own face bed)
-    const double rH = frcp(hH), rL = frcp(hL);
-    const double shH = fmax0((hH + zH) - zH), shL = fmax0((hL + zL) - zL);
-    const double uH = qxH * rH, vH = qyH * rH, uL = qxL * rL, vL = qyL * rL;
-    const double zb1 = (fminr(hH + zH, zH) - fminr(hL + zL, zL)) * i2s3;
-    const double hb0 = 0.5 * (shH + shL), hb1 = (shH - shL) * i2s3;
-    const double qxH2 = shH * uH, qxL2 = shL * uL, qyH2 = shH * vH, qyL2 = shL * vL;
-    const double qb0 = 0.5 * (qxH2 + qxL2), qb1 = (qxH2 - qxL2) * i2s3;
-    const double rb0 = 0.5 * (qyH2 + qyL2), rb1 = (qyH2 - qyL2) * i2s3;
-    // cotangents of the stored Gauss sums and of the source terms
-    const double gsb[3] = {-cc * (xdir ? mc[1] : mc[2]), -cc * (xdir ? mc[4] : mc[5]),
-                           -cc * (xdir ? mc[7] : mc[8])};
-    const double s0b = -(xdir ? mc[3] : mc[6]), s1b = -(xdir ? mc[4] : mc[8]);
-    // Gauss flux cotangents in the normal frame (y faces: normal momentum is y)
-    const double fbn[3] = {gsb[0], xdir ? gsb[1] : gsb[2], xdir ? gsb[2] : gsb[1]};
-    const double qn0 = xdir ? qb0 : rb0, qn1 = xdir ? qb1 : rb1, qt0 = xdir ? rb0 : qb0, qt1 = xdir ? rb1 : qb1;
-    double hpb, qnpb, qtpb, hmb, qnmb, qtmb;
-    gauss_rev(g, ht, hb0 + hb1, qn0 + qn1, qt0 + qt1, fbn, hpb, qnpb, qtpb);
-    gauss_rev(g, ht, hb0 - hb1, qn0 - qn1, qt0 - qt1, fbn, hmb, qnmb, qtmb);
-    // s0 = k2s3 hb0 zb1, s1 = k2s3 hb1 zb1 (zb1 does not depend on the coefficients here)
-    const double hb0b = hpb + hmb + s0b * k2s3 * zb1, hb1b = hpb - hmb + s1b * k2s3 * zb1;
-    const double qn0b = qnpb + qnmb, qn1b = qnpb - qnmb, qt0b = qtpb + qtmb, qt1b = qtpb - qtmb;
-    const double qb0b = xdir ? qn0b : qt0b, qb1b = xdir ? qn1b : qt1b;
-    const double rb0b = xdir ? qt0b : qn0b, rb1b = xdir ? qt1b : qn1b;
-    const double qxH2b = 0.5 * qb0b + i2s3 * qb1b, qxL2b = 0.5 * qb0b - i2s3 * qb1b;
-    const double qyH2b = 0.5 * rb0b + i2s3 * rb1b, qyL2b = 0.5 * rb0b - i2s3 * rb1b;
-    const double shHb = 0.5 * hb0b + i2s3 * hb1b + qxH2b * uH + qyH2b * vH;
-    const double shLb = 0.5 * hb0b - i2s3 * hb1b + qxL2b * uL + qyL2b * vL;
-    const double uHb = qxH2b * shH, vHb = qyH2b * shH, uLb = qxL2b * shL, vLb = qyL2b * shL;
-    // through the revision of each side
-    const double hHb = shHb - (uHb * uH + vHb * vH) * rH, qxHb = uHb * rH, qyHb = vHb * rH;
-    const double hLb = shLb - (uLb * uL + vLb * vL) * rL, qxLb = uLb * rL, qyLb = vLb * rL;
-    // high side: d/dU0 = 1, d/dU1d = sqrt(3); low side: 1, -sqrt(3)
-    nu[0] += hHb + hLb;
-    nu[3] += qxHb + qxLb;
-    nu[6] += qyHb + qyLb;
-    nu[1] += xdir ? s3 * (hHb - hLb) : 0.0;
-    nu[4] += xdir ? s3 * (qxHb - qxLb) : 0.0;
-    nu[7] += xdir ? s3 * (qyHb - qyLb) : 0.0;
-    nu[2] += xdir ? 0.0 : s3 * (hHb - hLb);
-    nu[5] += xdir ? 0.0 : s3 * (qxHb - qxLb);
-    nu[8] += xdir ? 0.0 : s3 * (qyHb - qyLb);
-  }
-
-  // the combination with the incoming cotangents, then the friction adjoint
+  // the local terms, the combination with the incoming cotangents, then the friction
+  // adjoint
 #pragma unroll
-  for (int q = 0; q < 9; ++q) nu[q] += a.cl * a.lam_c[q * n + c] + (a.extra ? a.extra[q * n + c] : 0.0);
+  for (int q = 0; q < 9; ++q)
+    nu[q] += nl[q] + a.cl * a.lam_c[q * n + c] + (a.extra ? a.extra[q * n + c] : 0.0);
   if (a.U_fr) {
     const double gn = adj_friction_cell(p, a.U_fr, c, a.dt_fr, nu);
     if (a.gman) a.gman[c] += gn;
