@@ -179,17 +179,12 @@ __device__ __forceinline__ void friction_rev(double gn2dt, double ht, double h, 
 // adjoint of the friction step at one cell: lam (the cotangent of F) becomes the
 // cotangent of U, lam_U = (dF/dU)^T lam_F; returns dJ/dn of the cell
 // ---------------------------------------------------------------------------------
-__device__ __forceinline__ double adj_friction_cell(const Params<double>& p, const double* __restrict__ U,
-                                                    long long c, double dt, double lam[9]) {
-  const long long n = p.n;
-  const double nm = p.manning ? p.manning[c] : p.n_scalar;
+__device__ __forceinline__ double adj_friction_cell(const Params<double>& p, const double u[9], double nm,
+                                                    double dt, double lam[9]) {
   if (!(nm > 0.0)) return 0.0;
-  double u[9], lf[9];
+  double lf[9];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    u[q] = U[q * n + c];
-    lf[q] = lam[q];
-  }
+  for (int q = 0; q < 9; ++q) lf[q] = lam[q];
   const double ht = p.h_tol;
   const double gdt = p.g * dt, gn2dt = gdt * (nm * nm);
   double gsum = 0.0;
@@ -529,6 +524,21 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY, 3) void adj_stage_kernel(Params<do
       else sm.fy[q][eslot - ADJ_NFX] = oe[q];
     }
   }
+  // the epilogue's global inputs of the cell, issued now so that they arrive while the
+  // face cotangents are gathered
+  double lcv[9], exv[9], ufr[9], nmf = 0.0, gm0 = 0.0;
+  int g0 = -1;
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      lcv[q] = a.lam_c[q * n + c];
+      exv[q] = a.extra ? a.extra[q * n + c] : 0.0;
+      ufr[q] = a.U_fr ? a.U_fr[q * n + c] : 0.0;
+    }
+    if (a.U_fr) nmf = p.manning ? p.manning[c] : p.n_scalar;
+    if (a.U_fr && a.gman) gm0 = a.gman[c];
+    if (a.gmap) g0 = a.gmap[c];
+  }
   __syncthreads();
   if (!active) return;  // no barrier follows
 
@@ -565,14 +575,12 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY, 3) void adj_stage_kernel(Params<do
   // the local terms, the combination with the incoming cotangents, then the friction
   // adjoint
 #pragma unroll
-  for (int q = 0; q < 9; ++q)
-    nu[q] += nl[q] + a.cl * a.lam_c[q * n + c] + (a.extra ? a.extra[q * n + c] : 0.0);
+  for (int q = 0; q < 9; ++q) nu[q] += nl[q] + a.cl * lcv[q] + exv[q];
   if (a.U_fr) {
-    const double gn = adj_friction_cell(p, a.U_fr, c, a.dt_fr, nu);
-    if (a.gman) a.gman[c] += gn;
+    const double gn = adj_friction_cell(p, ufr, nmf, a.dt_fr, nu);
+    if (a.gman) a.gman[c] = gm0 + gn;
   }
-  if (a.gmap)
-    for (int gg = a.gmap[c]; gg >= 0; gg = a.gnext[gg]) nu[0] += a.seed[gg];
+  for (int gg = g0; gg >= 0; gg = a.gnext[gg]) nu[0] += a.seed[gg];
 #pragma unroll
   for (int q = 0; q < 9; ++q) a.out[q * n + c] = nu[q];
   if (bad) atomicOr(a.regime, bad);
