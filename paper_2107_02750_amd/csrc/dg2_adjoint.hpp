@@ -390,28 +390,55 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY, 3) void adj_stage_kernel(Params<do
   const int tiles_x = (nx + ADJ_TX - 1) / ADJ_TX;
   const int i0 = (int(blockIdx.x) % tiles_x) * ADJ_TX, j0 = (int(blockIdx.x) / tiles_x) * ADJ_TY;
   const int tid = threadIdx.x;
-  for (int r = tid; r < ADJ_RB; r += ADJ_TX * ADJ_TY) {  // box cells, clamped to the domain
-    int bi = i0 - 1 + r % ADJ_RX, bj = j0 - 1 + r / ADJ_RX;
-    bi = bi < 0 ? 0 : (bi >= nx ? nx - 1 : bi);
-    bj = bj < 0 ? 0 : (bj >= ny ? ny - 1 : bj);
-    const long long k = (long long)bj * nx + bi;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      sm.v[q][r] = a.V[q * n + k];
-      sm.m[q][r] = a.alpha * a.lam[q * n + k];
-    }
-  }
-  __syncthreads();
   const int ta = tid % ADJ_TX, tb = tid / ADJ_TX;
   const int i = i0 + ta, j = j0 + tb;
   const bool active = i < nx && j < ny;
+  // box cells (clamped to the domain), two per thread at most, and the cell's four bed
+  // vertices: all loads issued before any is waited on
+  constexpr int NT = ADJ_TX * ADJ_TY, BIT = (ADJ_RB + NT - 1) / NT;
+  static_assert(BIT == 2, "two box cells per thread");
+  double bv[BIT][9], bm[BIT][9];
+#pragma unroll
+  for (int it = 0; it < BIT; ++it) {
+    const int r = tid + it * NT;
+    if (r < ADJ_RB) {
+      int bi = i0 - 1 + r % ADJ_RX, bj = j0 - 1 + r / ADJ_RX;
+      bi = bi < 0 ? 0 : (bi >= nx ? nx - 1 : bi);
+      bj = bj < 0 ? 0 : (bj >= ny ? ny - 1 : bj);
+      const long long k = (long long)bj * nx + bi;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        bv[it][q] = a.V[q * n + k];
+        bm[it][q] = a.lam[q * n + k];
+      }
+    }
+  }
+  double zsw = 0.0, zse = 0.0, znw = 0.0, zne = 0.0;  // the cell's vertices
+  if (active) {
+    const long long v0 = (long long)j * (nx + 1) + i;
+    zsw = p.zv[v0];
+    zse = p.zv[v0 + 1];
+    znw = p.zv[v0 + nx + 1];
+    zne = p.zv[v0 + nx + 2];
+  }
+#pragma unroll
+  for (int it = 0; it < BIT; ++it) {
+    const int r = tid + it * NT;
+    if (r < ADJ_RB) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        sm.v[q][r] = bv[it][q];
+        sm.m[q][r] = a.alpha * bm[it][q];
+      }
+    }
+  }
+  __syncthreads();
   const int iend = nx < i0 + ADJ_TX ? nx : i0 + ADJ_TX, jend = ny < j0 + ADJ_TY ? ny : j0 + ADJ_TY;
   const long long c = (long long)j * nx + i;
   const int cpos = (tb + 1) * ADJ_RX + ta + 1;
   const double g = p.g, ht = p.h_tol, s3 = K<double>::s3;
   const double idx = 1.0 / p.dx, cc = -s3 * idx, i2s3 = K<double>::inv_2s3;
   const double k2s3 = 2.0 * s3 * g * idx;
-  auto zvv = [&](int iv, int jv) { return p.zv[(long long)jv * (nx + 1) + iv]; };
   int bad = 0;
 
   // local terms of the cell's own L (Gauss fluxes and bed source), per direction:
@@ -434,8 +461,8 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY, 3) void adj_stage_kernel(Params<do
       const double hH = vc[0] + s3 * c1, qxH = vc[3] + s3 * c4, qyH = vc[6] + s3 * c7;
       const double hL = vc[0] - s3 * c1, qxL = vc[3] - s3 * c4, qyL = vc[6] - s3 * c7;
       double zH, zL;
-      if (xdir) { zH = 0.5 * (zvv(i + 1, j + 1) + zvv(i + 1, j)); zL = 0.5 * (zvv(i, j + 1) + zvv(i, j)); }
-      else { zH = 0.5 * (zvv(i, j + 1) + zvv(i + 1, j + 1)); zL = 0.5 * (zvv(i, j) + zvv(i + 1, j)); }
+      if (xdir) { zH = 0.5 * (zne + zse); zL = 0.5 * (znw + zsw); }
+      else { zH = 0.5 * (znw + zne); zL = 0.5 * (zsw + zse); }
       // revised sides (the bed of each side is its own face bed)
       const double rH = frcp(hH), rL = frcp(hL);
       const double shH = fmax0((hH + zH) - zH), shL = fmax0((hL + zL) - zL);
