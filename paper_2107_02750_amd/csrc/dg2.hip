@@ -201,6 +201,7 @@ Params<R> params(const dg2_ctx* c) {
   p.parity = c->parity;
   p.fv1 = c->fv1 ? 1 : 0;
   p.dx = R(c->cfg.dx);
+  p.idx = R(1) / p.dx;
   p.g = R(c->cfg.g);
   p.h_tol = R(c->cfg.h_tol);
   p.n_scalar = R(c->manning_scalar);

@@ -268,7 +268,7 @@ struct AdjFace {
   bool xdir;
   int posL, posR;     // box positions of the low and high cells
   bool realL, realR;  // in the domain (at most one is not: a boundary face)
-  int va, vb;         // the face's first bed vertex
+  double zf;          // face bed: the mean of its two vertices
   int line;           // row (x face) or column (y face) of the face
 };
 
@@ -276,17 +276,16 @@ __device__ __forceinline__ void adj_face(const Params<double>& p, const AdjArgs&
                                          const AdjFace& F, double lo[3], double hi[3], int& bad) {
   const int nx = p.nx, ny = p.ny;
   const double g = p.g, ht = p.h_tol, s3 = K<double>::s3;
-  const double idx = 1.0 / p.dx, cc = -s3 * idx;
+  const double idx = p.idx, cc = -s3 * idx;
   const double slack = dsqrt(p.gd * p.htd);
   const bool xdir = F.xdir;
   auto V = [&](int pos, int q) { return sm.v[q][pos]; };
   auto mu = [&](int pos, int q) { return sm.m[q][pos]; };
-  auto zvv = [&](int iv, int jv) { return p.zv[(long long)jv * (nx + 1) + iv]; };
   auto umean = [&](int pos, bool xv) {
     const double h0 = V(pos, 0);
     return h0 > ht ? V(pos, xv ? 3 : 6) * frcp(h0) : 0.0;
   };
-  const double zf = 0.5 * (zvv(F.va, F.vb) + (xdir ? zvv(F.va, F.vb + 1) : zvv(F.va + 1, F.vb)));
+  const double zf = F.zf;
   // velocity caps: the larger mean-velocity magnitude of the face's cells plus the slack
   const int pL = F.realL ? F.posL : F.posR, pR = F.realR ? F.posR : F.posL;
   const double ucap = fmax(fabs(umean(pL, true)), fabs(umean(pR, true))) + slack;
@@ -421,6 +420,20 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY, 3) void adj_stage_kernel(Params<do
     znw = p.zv[v0 + nx + 1];
     zne = p.zv[v0 + nx + 2];
   }
+  // the extra face of threads 0..TY+TX-1 (below): its two vertices
+  const int iend = nx < i0 + ADJ_TX ? nx : i0 + ADJ_TX, jend = ny < j0 + ADJ_TY ? ny : j0 + ADJ_TY;
+  const int ejr = j0 + tid, eic = i0 + tid - ADJ_TY;
+  const bool ex = tid < ADJ_TY && ejr < ny, ey = tid >= ADJ_TY && tid < ADJ_TY + ADJ_TX && eic < nx;
+  double ez0 = 0.0, ez1 = 0.0;
+  if (ex) {
+    const long long v0 = (long long)ejr * (nx + 1) + iend;
+    ez0 = p.zv[v0];
+    ez1 = p.zv[v0 + nx + 1];
+  } else if (ey) {
+    const long long v0 = (long long)jend * (nx + 1) + eic;
+    ez0 = p.zv[v0];
+    ez1 = p.zv[v0 + 1];
+  }
 #pragma unroll
   for (int it = 0; it < BIT; ++it) {
     const int r = tid + it * NT;
@@ -433,11 +446,10 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY, 3) void adj_stage_kernel(Params<do
     }
   }
   __syncthreads();
-  const int iend = nx < i0 + ADJ_TX ? nx : i0 + ADJ_TX, jend = ny < j0 + ADJ_TY ? ny : j0 + ADJ_TY;
   const long long c = (long long)j * nx + i;
   const int cpos = (tb + 1) * ADJ_RX + ta + 1;
   const double g = p.g, ht = p.h_tol, s3 = K<double>::s3;
-  const double idx = 1.0 / p.dx, cc = -s3 * idx, i2s3 = K<double>::inv_2s3;
+  const double idx = p.idx, cc = -s3 * idx, i2s3 = K<double>::inv_2s3;
   const double k2s3 = 2.0 * s3 * g * idx;
   int bad = 0;
 
@@ -512,28 +524,22 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY, 3) void adj_stage_kernel(Params<do
   // faces of the tile's last column and the north faces of its last row
   double ow[6], os[6], oe[6];
   if (active) {
-    const AdjFace fw{true, cpos - 1, cpos, i > 0, true, i, j, j};
+    const AdjFace fw{true, cpos - 1, cpos, i > 0, true, 0.5 * (zsw + znw), j};
     adj_face(p, a, sm, fw, ow, ow + 3, bad);
-    const AdjFace fs{false, cpos - ADJ_RX, cpos, j > 0, true, i, j, i};
+    const AdjFace fs{false, cpos - ADJ_RX, cpos, j > 0, true, 0.5 * (zsw + zse), i};
     adj_face(p, a, sm, fs, os, os + 3, bad);
   }
   int eslot = -1;  // 0..NFX-1: an x face, NFX + ...: a y face
-  if (tid < ADJ_TY) {
-    const int jr = j0 + tid;
-    if (jr < ny) {
-      const int pos = (tid + 1) * ADJ_RX + (iend - i0);  // the low cell, column iend - 1
-      const AdjFace fe{true, pos, pos + 1, true, iend < nx, iend, jr, jr};
-      adj_face(p, a, sm, fe, oe, oe + 3, bad);
-      eslot = tid * (ADJ_TX + 1) + (iend - i0);
-    }
-  } else if (tid < ADJ_TY + ADJ_TX) {
-    const int ic = i0 + tid - ADJ_TY;
-    if (ic < nx) {
-      const int pos = (jend - j0) * ADJ_RX + (ic - i0) + 1;  // the low cell, row jend - 1
-      const AdjFace fn{false, pos, pos + ADJ_RX, true, jend < ny, ic, jend, ic};
-      adj_face(p, a, sm, fn, oe, oe + 3, bad);
-      eslot = ADJ_NFX + (jend - j0) * ADJ_TX + (ic - i0);
-    }
+  if (ex) {
+    const int pos = (tid + 1) * ADJ_RX + (iend - i0);  // the low cell, column iend - 1
+    const AdjFace fe{true, pos, pos + 1, true, iend < nx, 0.5 * (ez0 + ez1), ejr};
+    adj_face(p, a, sm, fe, oe, oe + 3, bad);
+    eslot = tid * (ADJ_TX + 1) + (iend - i0);
+  } else if (ey) {
+    const int pos = (jend - j0) * ADJ_RX + (eic - i0) + 1;  // the low cell, row jend - 1
+    const AdjFace fn{false, pos, pos + ADJ_RX, true, jend < ny, 0.5 * (ez0 + ez1), eic};
+    adj_face(p, a, sm, fn, oe, oe + 3, bad);
+    eslot = ADJ_NFX + (jend - j0) * ADJ_TX + (eic - i0);
   }
   __syncthreads();  // the box is no longer read: its LDS takes the face cotangents
   if (active) {

@@ -106,7 +106,7 @@ struct Params {
   double* ledger;              // per tile: in, out, clip, unused
   long long n;                 // nx * ny
   int nx, ny, tx, ty, tiles_x, n_tiles, per_xcd, nsegs, max_knots, limiter, parity, fv1;
-  R dx, g, h_tol, n_scalar;
+  R dx, idx, g, h_tol, n_scalar;  // idx = 1 / dx (rounded once, on the host)
   double dxd, gd, cfl, htd, dt_dry, dt_max, t_end;
   double dt_fix;               // > 0: the step takes exactly this dt (a replayed schedule)
 };
@@ -881,7 +881,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   R sx0 = R(0), sx1 = R(0), sy0 = R(0), sy1 = R(0);
   const R g = p.g;
   if (active) {
-    const R k2s3 = R(2) * s3 * g * (R(1) / p.dx);
+    const R k2s3 = R(2) * s3 * g * p.idx;
     {  // x direction
       const R hb0 = R(0.5) * (se_.h + sw_.h), hb1 = (se_.h - sw_.h) * K<R>::inv_2s3;
       const R qxE = se_.h * se_.u, qxW = sw_.h * sw_.u, qyE = se_.h * se_.v, qyW = sw_.h * sw_.v;
@@ -916,7 +916,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   // neither they nor va stay live through the face phase; stage 1 publishes V^n here
   R w[9];
   {
-    const R c = -s3 * (R(1) / p.dx);
+    const R c = -s3 * p.idx;
     const R Lg[9] = {R(0), -c * gx[0], -c * gy[0], -sx0, -c * gx[1] - sx1, -c * gy[1],
                      -sy0, -c * gx[2], -c * gy[2] - sy1};
 #pragma unroll
@@ -1035,7 +1035,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
     const R fe[3] = {sm.fx[0][xw + 1], sm.fx[1][xw + 1], sm.fx[2][xw + 1]};
     const R fs[3] = {sm.fy[0][ys], sm.fy[1][ys], sm.fy[2][ys]};
     const R fn[3] = {sm.fy[0][ys + TX], sm.fy[1][ys + TX], sm.fy[2][ys + TX]};
-    const R idx = R(1) / p.dx;
+    const R idx = p.idx;
     const R c = -s3 * idx;
     R L[9];
     L[0] = -(fe[0] - fw[0]) * idx + -(fn[0] - fs[0]) * idx;
@@ -1389,7 +1389,7 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     const R zs = inside ? fmaxr(z, sm.z0[nb]) : z;
     fv1_side(h, z, zs, hs, zss);
   };
-  const R idx = R(1) / p.dx;
+  const R idx = p.idx;
   R L0 = R(0), L1 = R(0), L2 = R(0);
 
   // ---- phase 2: x faces (each west face once; the tile's east faces by halo items) ----
