@@ -10,13 +10,14 @@
 // plus the parameter terms: Manning n through friction, the inflow discharge Q(t)
 // through the inflow ghost states of both stages.
 //
-// (dL/dV)^T mu is gathered per cell: L of a cell depends on its own coefficients
-// through its four face sides (Gauss fluxes, bed source, and the four face fluxes)
-// and on a neighbour's only through the shared face flux. So each cell needs the
-// cotangent of each of its face fluxes (collected from the cell and the neighbour),
-// which it takes back through the same face, flux and friction formulas as the
-// forward kernels (reverse mode written out per formula, recomputing the forward
-// values) to its own face limits, and from there to its nine coefficients.
+// (dL/dV)^T mu: L of a cell depends on its own coefficients through its four face
+// sides (Gauss fluxes, bed source, and the four face fluxes) and on a neighbour's only
+// through the shared face flux. Each face therefore takes the cotangent of its flux
+// (from mu of the two cells that share it) back through the same flux, ghost and
+// revision formulas as the forward kernels (reverse mode written out per formula,
+// recomputing the forward values) to the face limits of both cells; each cell adds
+// the cotangents of its four face limits, its own Gauss and source terms and the
+// friction, and maps them to its nine coefficients.
 //
 // The regime is checked while the adjoint runs: a cell at or below h_tol, a face
 // depth not above zero, or an active face-velocity cap set a flag (the derivative
