@@ -7,7 +7,8 @@ Checked: the recorded gauge depths (1e-12 relative), the gradients of a gauge mi
 with respect to the per-cell Manning n (summed over zones) and the hydrograph knots
 (1e-7 relative to the largest component) and the initial state (1e-6), also with wall
 edges and a fixed-state segment, independence from the checkpoint spacing (bit for
-bit), the torch.autograd.Function wrapper, and the regime check. Measured agreement on this case: 2e-9 (zones), 3e-9 (knots),
+bit), a grid whose last tile column and row are partial, the torch.autograd.Function
+wrapper, and the regime check. Measured agreement on this case: 2e-9 (zones), 3e-9 (knots),
 2.5e-8 (initial state, largest at boundary cells); over 5 to 40 steps it does not
 grow. The gradients are sums over cells and steps with cancellation that the two
 sides form in different orders on states that differ in the last bits; the larger
@@ -143,6 +144,34 @@ def test_adjoint_with_walls_and_a_fixed_segment(dg2):
     eq = np.abs(gq - gq_ref).max() / np.abs(gq_ref).max()
     eu = np.abs(gu - gu_ref).max() / np.abs(gu_ref).max()
     print(f"walls + fixed segment: zones {ez:.2e}, knots {eq:.2e}, U0 {eu:.2e}", flush=True)
+    assert ez <= 1e-7 and eq <= 1e-7 and eu <= 1e-6
+
+
+def test_adjoint_on_ragged_tiles(dg2):
+    """A 37 x 37 grid: the last tile column (5 of 32 cells) and the last tile row (5 of
+    8) are partial, so the faces on the east and north sides of the active cells of
+    those tiles come from the threads that take the tile's extra faces, next to the
+    domain's edges (transmissive east, wall north) and inside it. (A fixed-state
+    segment on this grid's east edge drives face velocities past their cap in the CPU
+    reference as well, outside the regime.)"""
+    n = 37
+    base = S.adjoint_case(n=n, dx=5.0, t_span=4.0, n_knots=8)
+    sc = base.replace(edge_kind=(S.TRANSMISSIVE, S.TRANSMISSIVE, S.WALL, S.WALL))
+    dts = schedule(sc, 20)
+    gi = gauges(n)
+    href = href_of(sc, dts, gi)
+    _, hs_ref, gz_ref, gq_ref, gu_ref = reference(sc, dts, gi, href)
+    sim = dg2.DG2(sc, dg2.FP64)
+    tape = dg2.Tape(sim, dts, gi)
+    hs = tape.forward()
+    assert np.abs(hs - hs_ref).max() <= 1e-12 * np.abs(hs_ref).max()
+    gm, gq, gu = tape.backward(2.0 * (hs - href), len(sc.boundaries[0].q_knots))
+    zi = S.zone_index(n, 4)
+    gz = np.array([gm.reshape(-1)[zi.reshape(-1) == z].sum() for z in range(16)])
+    ez = np.abs(gz - gz_ref).max() / np.abs(gz_ref).max()
+    eq = np.abs(gq - gq_ref).max() / np.abs(gq_ref).max()
+    eu = np.abs(gu - gu_ref).max() / np.abs(gu_ref).max()
+    print(f"ragged tiles: zones {ez:.2e}, knots {eq:.2e}, U0 {eu:.2e}", flush=True)
     assert ez <= 1e-7 and eq <= 1e-7 and eu <= 1e-6
 
 
