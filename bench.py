@@ -328,7 +328,7 @@ def main():
                     help="also run one device-to-device copy of this many MiB (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the step would shard by 2D domain decomposition with halo exchange).",
               file=sys.stderr)
         sys.exit(2)

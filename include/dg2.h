@@ -58,7 +58,7 @@ enum {
   DG2_E_DEVICE = -2,     /* a HIP call failed (message names it) */
   DG2_E_NUMERIC = -3,    /* NaN in the state, or the time step fell below 1e-12 s */
   DG2_E_STATE = -4,      /* state blob of the wrong size, precision or grid */
-  DG2_E_UNSUPPORTED = -5 /* valid request this build does not support */
+  DG2_E_UNSUPPORTED = -5 /* valid request the library does not support */
 };
 
 enum { DG2_FP64 = 0, DG2_FP32 = 1 };

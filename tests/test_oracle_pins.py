@@ -187,6 +187,15 @@ def test_mass_ledger_open_domain_with_inflow_and_clipping():
 
 def test_stoker_closed_form_values():
     hm, um, xs, xa, xb = _golden("stoker_textbook.txt")[0]
+    # the stored values against the relations that define them: the left rarefaction's
+    # Riemann invariant, mass and momentum across the right shock, and the wave positions
+    hl, hr, x0, t = 1.0, 0.5, 50.0, 2.5
+    assert abs(um - 2.0 * (np.sqrt(G * hl) - np.sqrt(G * hm))) <= 2e-6
+    s = hm * um / (hm - hr)
+    assert abs(hm * um * um + 0.5 * G * (hm * hm - hr * hr) - s * hm * um) <= 1e-5
+    assert abs(xs - (x0 + s * t)) <= 1e-4
+    assert abs(xa - (x0 - np.sqrt(G * hl) * t)) <= 1e-4
+    assert abs(xb - (x0 + (um - np.sqrt(G * hm)) * t)) <= 1e-4
     _, _, info = CF.stoker(np.array([0.0]), 2.5, 1.0, 0.5, 50.0, G)
     assert info["hm"] == pytest.approx(hm, abs=1e-7)
     assert info["um"] == pytest.approx(um, abs=1e-7)
