@@ -561,6 +561,9 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   // the other, they cost a memory round trip each.
   const R dT = (sizeof(R) == 4 && p.datum) ? p.datum[tile] : R(0);
   const R* __restrict__ src = STAGE == 1 ? p.uin : p.ui;
+  // FP32: the wave issues its phase-1 loads at raised priority (measured 1.8 % faster
+  // for both FP32 stages; no gain for FP64)
+  if constexpr (sizeof(R) == 4) __builtin_amdgcn_s_setprio(3);
   const StepLoads sl = step_loads(p);  // in flight with the tile's loads below
   double t, dt, t_next, dt_cfl;        // the step's times, formed once those are issued
   R dtr;
@@ -678,6 +681,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
     halo_item(tid, ha, hbb, hnp, hxd);
     load_raw(cell_of(ha, hbb), vb, nmb);
   }
+  if constexpr (sizeof(R) == 4) __builtin_amdgcn_s_setprio(0);
   // the step's time and time step (the same in every block), read only now, with the
   // tile's loads already in flight
   step_time(p, sl, t, dt, t_next, dt_cfl);
