@@ -574,7 +574,10 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY, 3) void adj_stage_kernel(Params<do
     if (a.gmap) g0 = a.gmap[c];
   }
   __syncthreads();
-  if (!active) return;  // no barrier follows
+  if (!active) {  // no barrier follows; an extra face may still have set a flag
+    if (bad) atomicOr(a.regime, bad);
+    return;
+  }
 
   // the cell's face-limit cotangents (W, E, S, N), chained to the coefficients as
   // d/dU0 = 1, d/dU1 = sgn sqrt(3) (sgn + for the high side of the cell)

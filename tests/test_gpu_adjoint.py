@@ -219,3 +219,26 @@ def test_regime_and_argument_checks(dg2):
     with pytest.raises(dg2.DG2Error) as e:
         dg2.Tape(dg2.DG2(sc, dg2.FP64), dts, [N * N])
     assert e.value.code == dg2.E_ARG
+
+
+def test_regime_flag_from_a_partial_tile_edge_face(dg2):
+    """On a 37 x 37 grid a fixed-state face on the east edge at row 15 drives the face
+    velocity of the last cell of that row past its cap (the CPU reference shows it
+    there and nowhere else in the first steps). That face is one of its tile's extra
+    faces, taken by a thread whose own cell lies outside the grid (the tile has 5
+    active columns); its flag must still reach the regime check."""
+    n = 37
+    base = S.adjoint_case(n=n, dx=5.0, t_span=4.0, n_knots=8)
+    P = Oracle(base).planes()
+    h_b = float(P[0][15:16, -1].mean()) + 0.02
+    u_b = float((P[3] / P[0])[15:16, -1].mean())
+    sc = base.replace(edge_kind=(S.TRANSMISSIVE, S.TRANSMISSIVE, S.WALL, S.WALL),
+                      boundaries=base.boundaries + [S.Boundary(S.E, S.FIXED, 15, 16, h_b=h_b,
+                                                               u_b=u_b, v_b=0.01)])
+    dts = schedule(sc, 4)
+    tape = dg2.Tape(dg2.DG2(sc, dg2.FP64), dts, gauges(n))
+    hs = tape.forward()
+    with pytest.raises(dg2.DG2Error) as e:
+        tape.backward(np.ones_like(hs), len(sc.boundaries[0].q_knots))
+    assert e.value.code == dg2.E_UNSUPPORTED
+    assert "velocity cap" in str(e.value)
