@@ -190,7 +190,7 @@ __device__ __forceinline__ double adj_friction_cell(const Params<double>& p, con
   const double gdt = p.g * dt, gn2dt = gdt * (nm * nm);
   double gsum = 0.0;
   // points: 0 centre; 1, 2: x +/-; 3, 4: y +/-
-#pragma unroll 1
+#pragma unroll
   for (int pt = 0; pt < 5; ++pt) {
     const int d = pt == 0 ? 0 : (pt <= 2 ? 1 : 2);
     const double sg = pt == 0 ? 0.0 : ((pt == 1 || pt == 3) ? 1.0 : -1.0);
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(ADJ_TX * ADJ_TY, 3) void adj_stage_kernel(Params<do
       mc[q] = sm.m[q][cpos];
     }
     if (!(vc[0] > ht)) bad |= 1;
-#pragma unroll 1
+#pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
       const bool xdir = dir == 0;
       const double c1 = xdir ? vc[1] : vc[2], c4 = xdir ? vc[4] : vc[5], c7 = xdir ? vc[7] : vc[8];
