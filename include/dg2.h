@@ -181,10 +181,13 @@ int dg2_state_bytes(const dg2_ctx *c, size_t *bytes);
 int dg2_get_state(dg2_ctx *c, void *host_dst);
 int dg2_set_state(dg2_ctx *c, const void *host_src);
 
-/* Per-kernel timing with HIP events on the context's stream. While enabled, every
- * stage kernel launch is bracketed by events; dg2_get_timing waits and returns the
- * number of timed steps and the mean milliseconds per launch of the stage-1 and
- * stage-2 kernels since timing was (re)enabled. */
+/* Per-kernel timing with HIP events on the context's stream. on = 0 disables it; with
+ * on = k > 0 the stage kernel launches of every k-th step (the first, the (k+1)-th, ...)
+ * are bracketed by events (each event record costs the stream a few microseconds, so a
+ * throughput measurement samples); on < 0 is DG2_E_ARG. dg2_get_timing waits and
+ * returns the number of timed steps and the mean milliseconds per launch of the
+ * stage-1 and stage-2 kernels (FV1: its one kernel as stage 1) over those steps since
+ * timing was (re)enabled. */
 int dg2_set_timing(dg2_ctx *c, int32_t on);
 int dg2_get_timing(dg2_ctx *c, int64_t *steps, double *ms_stage1, double *ms_stage2);
 

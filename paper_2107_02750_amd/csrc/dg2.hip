@@ -122,6 +122,8 @@ struct dg2_ctx {
   Ctrl* h_ctrl;        // pinned mirror of the control block
   double* h_scal;      // pinned totals
   bool timing;
+  int timing_every;         // with timing: bracket every timing_every-th step
+  long long timing_count;   // steps launched since timing was (re)enabled
   std::vector<hipEvent_t> ev;  // 3 events per timed step
   size_t ev_used;
   int64_t t_steps;
@@ -230,7 +232,7 @@ struct LaunchStep {
   p.t_end = t_end;
   const dim3 grid(c->L.grid), block(c->L.threads);
   hipEvent_t* e = nullptr;
-  if (c->timing) {
+  if (c->timing && c->timing_count++ % c->timing_every == 0) {
     if (c->ev_used + 3 > c->ev.size()) {
       const size_t old = c->ev.size();
       c->ev.resize(old + 3 * 1024);
@@ -255,7 +257,7 @@ struct LaunchStep {
     p.t_end = t_end;
     const dim3 grid(c->L.grid), block(c->L.threads);
     hipEvent_t* e = nullptr;
-    if (c->timing) {
+    if (c->timing && c->timing_count++ % c->timing_every == 0) {
       if (c->ev_used + 3 > c->ev.size()) {
         const size_t old = c->ev.size();
         c->ev.resize(old + 3 * 1024);
@@ -828,6 +830,8 @@ int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, dou
   x->nsegs = n_bcs;
   x->parity = 0;
   x->timing = false;
+  x->timing_every = 1;
+  x->timing_count = 0;
   x->ev_used = 0;
   x->t_steps = 0;
   x->t_ms1 = x->t_ms2 = 0;
@@ -1045,7 +1049,10 @@ int dg2_set_state(dg2_ctx* c, const void* host_src) {
 int dg2_set_timing(dg2_ctx* c, int32_t on) {
   if (!c) return DG2_E_ARG;
   HIPC(c, hipStreamSynchronize(c->stream));
+  if (on < 0) return DG2_E_ARG;
   c->timing = on != 0;
+  c->timing_every = on > 0 ? on : 1;
+  c->timing_count = 0;
   c->ev_used = 0;
   c->t_steps = 0;
   c->t_ms1 = c->t_ms2 = 0;

@@ -294,8 +294,9 @@ class DG2:
         buf = C.create_string_buffer(blob, len(blob))
         self._check(self._lib.dg2_set_state(self._h, buf))
 
-    def set_timing(self, on: bool) -> None:
-        self._check(self._lib.dg2_set_timing(self._h, int(on)))
+    def set_timing(self, on, every: int = 1) -> None:
+        """Time the stage kernels of every `every`-th step with HIP events (off: on=False)."""
+        self._check(self._lib.dg2_set_timing(self._h, int(every) if on else 0))
 
     def timing(self) -> dict:
         s = C.c_int64()
