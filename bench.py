@@ -101,19 +101,20 @@ def timed_steps(sim, steps):
 
 
 def cpu_baseline(sc, budget_s):
-    """The FP64 CPU oracle on this host, stepping the same workload for about
-    budget_s seconds (at least one step)."""
+    """The FP64 CPU oracle on this host, stepping the same workload until budget_s
+    seconds have passed (at least one step) after two untimed steps."""
     import oracle
     o = oracle.Oracle(sc)
-    o.step()  # the first step also starts the threads and touches the memory
-    t0 = time.perf_counter()
+    o.step()  # the first two steps also start the threads and touch both state buffers
     o.step()
-    per = time.perf_counter() - t0
-    k = max(1, int(budget_s / max(per, 1e-9)))
     t1 = time.perf_counter()
-    for _ in range(k):
+    steps = 0
+    while True:
         o.step()
-    steps, secs = k, time.perf_counter() - t1
+        steps += 1
+        secs = time.perf_counter() - t1
+        if secs >= budget_s:
+            break
     return dict(value=sc.nx * sc.ny * steps / secs, unit="cell-updates/s",
                 cores=oracle.threads(), kind="oracle",
                 sample=f"{steps} FP64 oracle steps of the same {sc.nx}x{sc.ny} all-wet "
