@@ -73,6 +73,7 @@ def load():
     lib.dg2ref_threads.argtypes = []
     lib.dg2ref_threads.restype = C.c_int
     lib.dg2ref_limit.argtypes = [vp, _dp, _dp]
+    lib.dg2ref_friction.argtypes = [vp, _dp, C.c_double, _dp]
     _lib = lib
     return lib
 
@@ -186,6 +187,13 @@ class Oracle:
         st = _f64(state).reshape(9, self.ny, self.nx)
         out = np.empty_like(st)
         self._check(self._lib.dg2ref_limit(self._h, _ptr(st), _ptr(out)))
+        return out
+
+    def friction(self, state: np.ndarray, dt: float) -> np.ndarray:
+        """The friction update alone (centre and Gauss points) of a 9-plane state."""
+        st = _f64(state).reshape(9, self.ny, self.nx)
+        out = np.empty_like(st)
+        self._check(self._lib.dg2ref_friction(self._h, _ptr(st), float(dt), _ptr(out)))
         return out
 
 

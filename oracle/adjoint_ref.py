@@ -12,7 +12,7 @@ Manning n and the inflow hydrograph knots:
   friction at the centre and the Gauss points (split implicit, one Newton step),
   face limits (eq 2), the temporary revision with the face bed (vertex mean), the
   face-velocity cap, boundary ghosts (transmissive, wall, fixed state, inflow Q(t)),
-  HLL fluxes, the operator L with 2-point Gauss fluxes and the bed source,
+  HLL fluxes (an inflow face carries the inflow state's own flux), the operator L with 2-point Gauss fluxes and the bed source,
   RK2: U_int = V + dt L(V, t), U_next = (V + U_int + dt L(U_int, t + dt)) / 2.
 The time steps are given (a replayed schedule), not differentiated. The regime is
 checked on every stage input; a violation raises.
@@ -185,7 +185,24 @@ class WetDG2:
         fl = [cat(us(g0[k]), X) for k, X in enumerate((Hh, Hn, Ht))]
         fr = [cat(X, us(g1[k])) for k, X in enumerate((Lh, Ln, Lt))]
         F = self.hll(fl[0], fl[1], fl[2], fr[0], fr[1], fr[2])
+        # an inflow face carries the inflow (ghost) state's own physical flux
+        for e, gs, sl_ in ((edges[0], g0, first), (edges[1], g1, last)):
+            m = torch.as_tensor(self.kind[e] == INFLOW)
+            if not bool(m.any()):
+                continue
+            P = self.phys(*gs)
+            F = [self._put(F[k], sl_, torch.where(us(m), us(P[k]), F[k][sl_]))
+                 for k in range(3)]
         return F, (Hh, Hn, Ht, Hz), (Lh, Ln, Lt, Lz)
+
+    @staticmethod
+    def _put(a, sl_, v):
+        b = a.clone()
+        b[sl_] = v
+        return b
+
+    def phys(self, h, un, ut):
+        return [h * un, h * un * un + 0.5 * self.g * h * h, h * un * ut]
 
     def operator(self, V, t, qknots):
         """L(V) for a stage input V (9, ny, nx) at stage time t."""

@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libdg2ref.so")
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "dg2ref.c")
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+    cmd = ["gcc", "-std=c11", "-O3", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
            "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -176,9 +176,11 @@ static void pass_friction(dg2ref_ctx *c, const double *U, double dt, double *F) 
 /* ------------------------------------------------------------------------------ */
 /* Slope limiter and wet/dry fronts. The paper names no limiter; reading: minmod    */
 /* (Cockburn-Shu form for the scaled basis) on the free-surface elevation           */
-/* eta = h + z and on qx, qy, one direction at a time, with ghost means at the      */
-/* domain edges copied from the edge cell. Limiting eta rather than h keeps still   */
-/* water still. A cell with h0 <= 0 is dry and all its coefficients become zero.    */
+/* eta = h + z and on qx, qy, one direction at a time. Beyond a domain edge the     */
+/* ghost cell copies the edge cell's depth and discharges and continues its bed     */
+/* plane, so uniform flow down a sloping bed passes an open edge unlimited.         */
+/* Limiting eta rather than h keeps still water still. A cell with h0 <= 0 is dry   */
+/* and all its coefficients become zero.                                            */
 /* Reading for wet/dry fronts: a cell whose mean depth is at most h_tol, or which   */
 /* has such a neighbour across one of its four faces, is made locally first order:  */
 /* its slopes become zero and the face revision sees its bed as flat at z0.         */
@@ -220,18 +222,32 @@ static void pass_limit(dg2ref_ctx *c, const double *S, double *out) {
       if (c->cfg.limiter)
       for (int d = 1; d <= 2; ++d) {
         size_t km, kp; /* neighbours in direction d, the cell itself at an edge */
+        int at_lo, at_hi;
+        double zlo, zhi; /* the cell's bed at its low and high faces in direction d */
         if (d == 1) {
           km = (size_t)j * nx + (i > 0 ? i - 1 : i);
           kp = (size_t)j * nx + (i < nx - 1 ? i + 1 : i);
+          at_lo = i == 0;
+          at_hi = i == nx - 1;
+          zlo = zface_x(c, i, j);
+          zhi = zface_x(c, i + 1, j);
         } else {
           km = (size_t)(j > 0 ? j - 1 : j) * nx + i;
           kp = (size_t)(j < ny - 1 ? j + 1 : j) * nx + i;
+          at_lo = j == 0;
+          at_hi = j == ny - 1;
+          zlo = zface_y(c, i, j);
+          zhi = zface_y(c, i, j + 1);
         }
         const double *zs = (d == 1) ? c->z1x : c->z1y;
-        /* eta */
+        /* eta; beyond an edge the ghost cell has the edge cell's depth on the edge
+           cell's bed plane continued one cell out (its centre lies zhi - zlo above or
+           below z0), so a free surface parallel to a sloping bed stays unlimited */
         double e0 = S[PL(0, 0) * n + k] + c->z0[k];
-        double em = S[PL(0, 0) * n + km] + c->z0[km];
-        double ep = S[PL(0, 0) * n + kp] + c->z0[kp];
+        double em = at_lo ? S[PL(0, 0) * n + k] + (c->z0[k] - (zhi - zlo))
+                          : S[PL(0, 0) * n + km] + c->z0[km];
+        double ep = at_hi ? S[PL(0, 0) * n + k] + (c->z0[k] + (zhi - zlo))
+                          : S[PL(0, 0) * n + kp] + c->z0[kp];
         double e1 = S[PL(0, d) * n + k] + zs[k];
         double le = minmod3(e1, (ep - e0) / SQRT3, (e0 - em) / SQRT3);
         if (le != e1) out[PL(0, d) * n + k] = le - zs[k];
@@ -260,6 +276,12 @@ static void pass_limit(dg2ref_ctx *c, const double *S, double *out) {
 
 int dg2ref_limit(dg2ref_ctx *c, const double *state, double *out) {
   pass_limit(c, state, out);
+  return DG2REF_OK;
+}
+
+int dg2ref_friction(dg2ref_ctx *c, const double *state, double dt, double *out) {
+  if (!c || !state || !out || !(dt >= 0.0)) return DG2REF_E_ARG;
+  pass_friction(c, state, dt, out);
   return DG2REF_OK;
 }
 
@@ -323,6 +345,14 @@ void dg2ref_hll(double g, double hL, double unL, double utL, double hR, double u
     out[m] = (sR * FL[m] - sL * FR[m] + sL * sR * (UR[m] - UL[m])) / (sR - sL);
 }
 
+/* physical flux of a state (h, un, ut) through a face with normal n:
+ * [h un, h un^2 + g h^2 / 2, h un ut] */
+static void phys_flux(double g, double h, double un, double ut, double o[3]) {
+  o[0] = h * un;
+  o[1] = h * un * un + 0.5 * g * h * h;
+  o[2] = h * un * ut;
+}
+
 /* mean velocity of a cell, zero at or below h_tol */
 static double mean_vel(const double *S, size_t n, size_t k, int var, double ht) {
   double h0 = S[PL(0, 0) * n + k];
@@ -363,7 +393,10 @@ static double hydro(const seg_t *s, double t) {
  * unspecified boundary treatment: transmissive copies, a wall reflects the normal
  * velocity, a fixed state is imposed, and an inflow of Q(t) spread over the segment
  * enters at the larger of the interior depth and the critical depth of that
- * discharge. */
+ * discharge. The face flux is the HLL flux between the ghost and the interior side,
+ * except at an inflow face, which carries the inflow state's own physical flux: the
+ * hydrograph is then imposed exactly (mass flux Q(t) / width through every face of
+ * the segment) with the interior depth in the pressure term. */
 static void ghost(const dg2ref_ctx *c, const bface_t *b, double t, int normal_is_x,
                   double inward, double h, double un, double ut, double *gh, double *gun,
                   double *gut) {
@@ -437,8 +470,13 @@ static void pass_faces(dg2ref_ctx *c, const double *S, double t, double *in_rate
         ghost(c, &c->be[j], t, 1, -1.0, fc->lo.h, fc->lo.u, fc->lo.v, &gh, &gu, &gv);
         fc->hi.h = gh; fc->hi.u = gu; fc->hi.v = gv; fc->hi.z = zs;
       }
-      /* normal = x: (h, u, v) */
-      dg2ref_hll(g, fc->lo.h, fc->lo.u, fc->lo.v, fc->hi.h, fc->hi.u, fc->hi.v, fc->flux);
+      /* normal = x: (h, u, v); an inflow face carries the inflow state's own flux */
+      if (f == 0 && c->bw[j].kind == DG2REF_BC_INFLOW)
+        phys_flux(g, fc->lo.h, fc->lo.u, fc->lo.v, fc->flux);
+      else if (f == nx && c->be[j].kind == DG2REF_BC_INFLOW)
+        phys_flux(g, fc->hi.h, fc->hi.u, fc->hi.v, fc->flux);
+      else
+        dg2ref_hll(g, fc->lo.h, fc->lo.u, fc->lo.v, fc->hi.h, fc->hi.u, fc->hi.v, fc->flux);
     }
 #pragma omp parallel for schedule(static)
   for (int f = 0; f <= ny; ++f)
@@ -482,7 +520,12 @@ static void pass_faces(dg2ref_ctx *c, const double *S, double t, double *in_rate
       }
       /* normal = y: the normal velocity is v, the tangential one u */
       double o[3];
-      dg2ref_hll(g, fc->lo.h, fc->lo.v, fc->lo.u, fc->hi.h, fc->hi.v, fc->hi.u, o);
+      if (f == 0 && c->bs[i].kind == DG2REF_BC_INFLOW)
+        phys_flux(g, fc->lo.h, fc->lo.v, fc->lo.u, o);
+      else if (f == ny && c->bn[i].kind == DG2REF_BC_INFLOW)
+        phys_flux(g, fc->hi.h, fc->hi.v, fc->hi.u, o);
+      else
+        dg2ref_hll(g, fc->lo.h, fc->lo.v, fc->lo.u, fc->hi.h, fc->hi.v, fc->hi.u, o);
       fc->flux[0] = o[0];
       fc->flux[1] = o[2]; /* x-momentum is tangential here */
       fc->flux[2] = o[1];
@@ -736,7 +779,12 @@ static void fv1_faces(dg2ref_ctx *c, const double *S, double t, double *in_rate,
         ghost(c, &c->be[j], t, 1, -1.0, fc->lo.h, fc->lo.u, fc->lo.v, &gh, &gu, &gv);
         fc->hi.h = gh; fc->hi.u = gu; fc->hi.v = gv; fc->hi.z = zs;
       }
-      dg2ref_hll(g, fc->lo.h, fc->lo.u, fc->lo.v, fc->hi.h, fc->hi.u, fc->hi.v, fc->flux);
+      if (f == 0 && c->bw[j].kind == DG2REF_BC_INFLOW)
+        phys_flux(g, fc->lo.h, fc->lo.u, fc->lo.v, fc->flux);
+      else if (f == nx && c->be[j].kind == DG2REF_BC_INFLOW)
+        phys_flux(g, fc->hi.h, fc->hi.u, fc->hi.v, fc->flux);
+      else
+        dg2ref_hll(g, fc->lo.h, fc->lo.u, fc->lo.v, fc->hi.h, fc->hi.u, fc->hi.v, fc->flux);
     }
   for (int f = 0; f <= ny; ++f)
     for (int i = 0; i < nx; ++i) {
@@ -756,7 +804,12 @@ static void fv1_faces(dg2ref_ctx *c, const double *S, double t, double *in_rate,
         fc->hi.h = gh; fc->hi.v = gn; fc->hi.u = gt; fc->hi.z = zs;
       }
       double o[3];
-      dg2ref_hll(g, fc->lo.h, fc->lo.v, fc->lo.u, fc->hi.h, fc->hi.v, fc->hi.u, o);
+      if (f == 0 && c->bs[i].kind == DG2REF_BC_INFLOW)
+        phys_flux(g, fc->lo.h, fc->lo.v, fc->lo.u, o);
+      else if (f == ny && c->bn[i].kind == DG2REF_BC_INFLOW)
+        phys_flux(g, fc->hi.h, fc->hi.v, fc->hi.u, o);
+      else
+        dg2ref_hll(g, fc->lo.h, fc->lo.v, fc->lo.u, fc->hi.h, fc->hi.v, fc->hi.u, o);
       fc->flux[0] = o[0];
       fc->flux[1] = o[2];
       fc->flux[2] = o[1];

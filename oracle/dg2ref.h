@@ -109,6 +109,9 @@ int dg2ref_operator(dg2ref_ctx *c, const double *state, double t, double *L,
                     double *inflow_rate, double *outflow_rate);
 /* the limiter alone applied to a state (9 planes), written to out */
 int dg2ref_limit(dg2ref_ctx *c, const double *state, double *out);
+/* the friction update alone (centre and Gauss points, time step dt) applied to a
+ * state (9 planes) with the context's Manning n, written to out */
+int dg2ref_friction(dg2ref_ctx *c, const double *state, double dt, double *out);
 
 #ifdef __cplusplus
 }
