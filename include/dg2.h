@@ -251,24 +251,37 @@ const char *dg2_batch_last_error(const dg2_batch *b);
 void dg2_batch_destroy(dg2_batch *b);
 
 /* ---- Parameters for gradient studies ------------------------------------------
- * dg2_set_manning: replace the per-cell Manning plane (nx*ny host doubles, >= 0); the
- * context must have been created with one (else DG2_E_STATE).
+ * dg2_set_manning: replace the per-cell Manning plane (nx*ny doubles, >= 0 and finite,
+ * in host memory, or in device memory of the context's GPU if src_is_device; device
+ * values are checked on the device before they replace the plane); the context must
+ * have been created with one (else DG2_E_STATE); DG2_E_ARG for bad values.
  * dg2_set_hydrograph: replace the discharges of boundary segment seg's hydrograph
  * knots (host, as many values as it was created with, >= 0; knot times unchanged). */
-int dg2_set_manning(dg2_ctx *c, const double *manning);
+int dg2_set_manning(dg2_ctx *c, const double *manning, int32_t src_is_device);
 int dg2_set_hydrograph(dg2_ctx *c, int32_t seg, const double *q_knots);
+/* dg2_knot_count: the hydrograph knots of boundary segment seg (0 unless it is an
+ * inflow segment), or with seg = -1 of all segments together: the length of the
+ * dJ/dq array that dg2_tape_backward fills. DG2_E_ARG for a bad segment or pointer. */
+int dg2_knot_count(const dg2_ctx *c, int32_t seg, int32_t *n_knots);
 
 /* ---- Discrete adjoint (FP64, DG2, limiter off, fully wet flows) ------------------
- * A tape records a forward run of n_steps steps of a context with prescribed time
- * steps dts[k] (the replayed schedule: each step takes exactly dts[k]; choose them
- * within the CFL bound, e.g. from a previous run), keeping the state every
- * checkpoint_every steps (0: ceil(sqrt(n_steps))) and the depth h0 of n_gauges gauge
- * cells (indices j*nx + i) at every step, initial state included. dg2_tape_backward
- * then propagates dJ/dh (host, (n_steps+1) x n_gauges, row k = after k steps) back
- * through the recorded run, recomputing each segment between checkpoints, and returns
- * (host arrays, each may be NULL): dJ/dn for every cell (nx*ny), dJ/dq for every
- * hydrograph knot of every boundary segment in segment order (their total count), and
- * dJ/dU0 for the initial state (9 planes). It is the exact derivative of the recorded
+ * The adjoint of the step of Sect. 2.1.1 (eq 4, friction and L) for gradient studies;
+ * the paper has no adjoint, this is an extension. A tape records a forward run of
+ * n_steps steps of a context with prescribed time steps dts[k] (the replayed
+ * schedule: each step takes exactly dts[k]; choose them within the CFL bound, e.g.
+ * from a previous run), keeping the state every checkpoint_every steps
+ * (0: ceil(sqrt(n_steps))) and the depth h0 of n_gauges gauge cells (indices j*nx + i)
+ * at every step, initial state included: dg2_tape_forward writes them to gauge_h,
+ * (n_steps+1) x n_gauges doubles, host memory or device memory if dst_is_device. The
+ * Manning plane and the hydrograph knots in effect at dg2_tape_forward are copied into
+ * the tape, and the backward pass uses those, whatever the context holds by then.
+ * dg2_tape_backward then propagates dJ/dh ((n_steps+1) x n_gauges, row k = after k
+ * steps) back through the recorded run, recomputing each segment between checkpoints,
+ * and returns (each may be NULL): dJ/dn for every cell (nx*ny), dJ/dq for every
+ * hydrograph knot of every boundary segment in segment order (their total count, see
+ * dg2_knot_count; always host memory), and dJ/dU0 for the initial state (9 planes).
+ * With device_ptrs, dj_dh, grad_manning and grad_u0 are device memory of the
+ * context's GPU, else host memory. It is the exact derivative of the recorded
  * discrete run while every cell stays wet (h0 > h_tol), face depths stay positive and
  * no face-velocity cap binds; if the run leaves that regime the call fails with
  * DG2_E_UNSUPPORTED. The forward call advances the context like dg2_step; the tape
@@ -279,9 +292,9 @@ int dg2_set_hydrograph(dg2_ctx *c, int32_t seg, const double *q_knots);
 typedef struct dg2_tape dg2_tape;
 int dg2_tape_create(dg2_ctx *c, int32_t n_steps, const double *dts, const int32_t *gauges,
                     int32_t n_gauges, int32_t checkpoint_every, dg2_tape **out);
-int dg2_tape_forward(dg2_tape *tp, double *gauge_h);
+int dg2_tape_forward(dg2_tape *tp, double *gauge_h, int32_t dst_is_device);
 int dg2_tape_backward(dg2_tape *tp, const double *dj_dh, double *grad_manning, double *grad_q,
-                      double *grad_u0);
+                      double *grad_u0, int32_t device_ptrs);
 const char *dg2_tape_last_error(const dg2_tape *tp);
 void dg2_tape_destroy(dg2_tape *tp);
 

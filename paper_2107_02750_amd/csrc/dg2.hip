@@ -337,6 +337,65 @@ bool finite_all(const double* a, size_t n) {
 
 int edge_len(const dg2_config& c, int edge) { return edge <= DG2_EDGE_E ? c.ny : c.nx; }
 
+int why_fail(std::string& why, const char* fmt, ...) {
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  why = buf;
+  return 1;
+}
+
+// the boundary tables of a configuration: per boundary face its kind and segment
+// (W[ny], E[ny], S[nx], N[nx]), the segment table and the hydrograph knot table
+// (t[DG2_MAX_KNOTS] then q[DG2_MAX_KNOTS]); returns non-zero with a reason if a
+// segment is invalid
+int build_tables(const dg2_config& c, const dg2_boundary* bcs, int n_bcs, std::vector<int>& bface,
+                 std::vector<Seg>& segs, std::vector<double>& knots, std::string& why) {
+  if (n_bcs < 0 || n_bcs > DG2_MAX_SEGMENTS || (n_bcs > 0 && !bcs)) return why_fail(why, "bad boundary list");
+  bface.assign(2 * (size_t)(c.nx + c.ny), 0);
+  const size_t eoff[4] = {0, (size_t)c.ny, 2 * (size_t)c.ny, 2 * (size_t)c.ny + c.nx};
+  for (int e = 0; e < 4; ++e)
+    for (int f = 0; f < edge_len(c, e); ++f) bface[eoff[e] + f] = c.edge_kind[e];
+  segs.assign(DG2_MAX_SEGMENTS, Seg{});
+  knots.assign(2 * DG2_MAX_KNOTS, 0.0);
+  std::vector<char> covered(bface.size(), 0);
+  int kused = 0;
+  for (int s = 0; s < n_bcs; ++s) {
+    const dg2_boundary& b = bcs[s];
+    if (b.edge < 0 || b.edge > 3) return why_fail(why, "boundary %d: bad edge", s);
+    if (b.kind < 0 || b.kind > 3) return why_fail(why, "boundary %d: bad kind", s);
+    if (b.i0 < 0 || b.i1 > edge_len(c, b.edge) || b.i0 >= b.i1) return why_fail(why, "boundary %d: bad range", s);
+    Seg& g = segs[s];
+    g.kind = b.kind; g.edge = b.edge; g.i0 = b.i0; g.i1 = b.i1; g.k0 = 0; g.nk = 0;
+    g.width = (double)(b.i1 - b.i0) * c.dx;
+    g.h_b = b.h_b; g.u_b = b.u_b; g.v_b = b.v_b;
+    if (b.kind == DG2_BC_FIXED && (!(b.h_b >= 0) || !std::isfinite(b.h_b) || !std::isfinite(b.u_b) || !std::isfinite(b.v_b)))
+      return why_fail(why, "boundary %d: bad fixed state", s);
+    if (b.kind == DG2_BC_INFLOW) {
+      if (b.n_knots < 1 || !b.t_knots || !b.q_knots) return why_fail(why, "boundary %d: no hydrograph", s);
+      if (kused + b.n_knots > DG2_MAX_KNOTS) return why_fail(why, "too many hydrograph knots");
+      for (int k = 0; k < b.n_knots; ++k) {
+        if (!std::isfinite(b.t_knots[k]) || !std::isfinite(b.q_knots[k]) || b.q_knots[k] < 0)
+          return why_fail(why, "boundary %d: bad knot %d", s, k);
+        if (k > 0 && !(b.t_knots[k] > b.t_knots[k - 1])) return why_fail(why, "boundary %d: knots not increasing", s);
+        knots[kused + k] = b.t_knots[k];
+        knots[DG2_MAX_KNOTS + kused + k] = b.q_knots[k];
+      }
+      g.k0 = kused;
+      g.nk = b.n_knots;
+      kused += b.n_knots;
+    }
+    for (int f = b.i0; f < b.i1; ++f) {
+      if (covered[eoff[b.edge] + f]) return why_fail(why, "boundary %d overlaps another", s);
+      covered[eoff[b.edge] + f] = 1;
+      bface[eoff[b.edge] + f] = b.kind | ((s + 1) << 8);
+    }
+  }
+  return 0;
+}
+
 int check_config(const dg2_config* cfg) {
   if (!cfg) return fail(nullptr, DG2_E_ARG, "null config");
   if (cfg->nx < 1 || cfg->ny < 1) return DG2_E_ARG;
@@ -771,45 +830,12 @@ int dg2_init(const dg2_config* cfg, const double* zv, const double* manning, dou
     return bad(DG2_E_ARG, "bad init mode %d", init_mode);
   }
   // boundary table
-  if (n_bcs < 0 || n_bcs > DG2_MAX_SEGMENTS || (n_bcs > 0 && !bcs)) return bad(DG2_E_ARG, "bad boundary list");
-  std::vector<int> bface(2 * (size_t)(c.nx + c.ny));
-  const size_t eoff[4] = {0, (size_t)c.ny, 2 * (size_t)c.ny, 2 * (size_t)c.ny + c.nx};
-  for (int e = 0; e < 4; ++e)
-    for (int f = 0; f < edge_len(c, e); ++f) bface[eoff[e] + f] = c.edge_kind[e];
-  std::vector<Seg> segs(DG2_MAX_SEGMENTS);
-  std::vector<double> knots(2 * DG2_MAX_KNOTS, 0.0);
-  std::vector<char> covered(bface.size(), 0);
-  int kused = 0;
-  for (int s = 0; s < n_bcs; ++s) {
-    const dg2_boundary& b = bcs[s];
-    if (b.edge < 0 || b.edge > 3) return bad(DG2_E_ARG, "boundary %d: bad edge", s);
-    if (b.kind < 0 || b.kind > 3) return bad(DG2_E_ARG, "boundary %d: bad kind", s);
-    if (b.i0 < 0 || b.i1 > edge_len(c, b.edge) || b.i0 >= b.i1) return bad(DG2_E_ARG, "boundary %d: bad range", s);
-    Seg& g = segs[s];
-    g.kind = b.kind; g.edge = b.edge; g.i0 = b.i0; g.i1 = b.i1; g.k0 = 0; g.nk = 0;
-    g.width = (double)(b.i1 - b.i0) * c.dx;
-    g.h_b = b.h_b; g.u_b = b.u_b; g.v_b = b.v_b;
-    if (b.kind == DG2_BC_FIXED && (!(b.h_b >= 0) || !std::isfinite(b.h_b) || !std::isfinite(b.u_b) || !std::isfinite(b.v_b)))
-      return bad(DG2_E_ARG, "boundary %d: bad fixed state", s);
-    if (b.kind == DG2_BC_INFLOW) {
-      if (b.n_knots < 1 || !b.t_knots || !b.q_knots) return bad(DG2_E_ARG, "boundary %d: no hydrograph", s);
-      if (kused + b.n_knots > DG2_MAX_KNOTS) return bad(DG2_E_ARG, "too many hydrograph knots");
-      for (int k = 0; k < b.n_knots; ++k) {
-        if (!std::isfinite(b.t_knots[k]) || !std::isfinite(b.q_knots[k]) || b.q_knots[k] < 0)
-          return bad(DG2_E_ARG, "boundary %d: bad knot %d", s, k);
-        if (k > 0 && !(b.t_knots[k] > b.t_knots[k - 1])) return bad(DG2_E_ARG, "boundary %d: knots not increasing", s);
-        knots[kused + k] = b.t_knots[k];
-        knots[DG2_MAX_KNOTS + kused + k] = b.q_knots[k];
-      }
-      g.k0 = kused;
-      g.nk = b.n_knots;
-      kused += b.n_knots;
-    }
-    for (int f = b.i0; f < b.i1; ++f) {
-      if (covered[eoff[b.edge] + f]) return bad(DG2_E_ARG, "boundary %d overlaps another", s);
-      covered[eoff[b.edge] + f] = 1;
-      bface[eoff[b.edge] + f] = b.kind | ((s + 1) << 8);
-    }
+  std::vector<int> bface;
+  std::vector<Seg> segs;
+  std::vector<double> knots;
+  {
+    std::string why;
+    if (build_tables(c, bcs, n_bcs, bface, segs, knots, why)) return bad(DG2_E_ARG, "%s", why.c_str());
   }
   const Layout L = layout(c);
   if (!d_workspace || ws_bytes < L.total) return bad(DG2_E_ARG, "workspace needs %zu bytes", L.total);
@@ -1128,27 +1154,56 @@ int dg2_tile_grid(const dg2_config* cfg, int32_t* tile_x, int32_t* tile_y, int32
   return DG2_OK;
 }
 
-int dg2_set_manning(dg2_ctx* c, const double* manning) {
+int dg2_set_manning(dg2_ctx* c, const double* manning, int32_t src_is_device) {
   if (!c || !manning) return DG2_E_ARG;
   if (!c->has_manning) return fail(c, DG2_E_STATE, "context has no per-cell Manning plane");
-  for (size_t k = 0; k < c->n; ++k)
-    if (!(manning[k] >= 0) || !std::isfinite(manning[k])) return fail(c, DG2_E_ARG, "bad Manning n at cell %zu", k);
-  double* st = nullptr;
-  HIPC(c, hipMalloc(&st, c->n * sizeof(double)));
-  hipError_t e = hipMemcpyAsync(st, manning, c->n * sizeof(double), hipMemcpyHostToDevice, c->stream);
   const unsigned blocks = (unsigned)((c->n + 255) / 256);
+  const double* src = manning;
+  void* tmp = nullptr;  // host input: a staging copy; device input: the check flag
+  hipError_t e = hipSuccess;
+  if (!src_is_device) {
+    for (size_t k = 0; k < c->n; ++k)
+      if (!(manning[k] >= 0) || !std::isfinite(manning[k])) return fail(c, DG2_E_ARG, "bad Manning n at cell %zu", k);
+    HIPC(c, hipMalloc(&tmp, c->n * sizeof(double)));
+    e = hipMemcpyAsync(tmp, manning, c->n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    src = static_cast<const double*>(tmp);
+  } else {
+    HIPC(c, hipMalloc(&tmp, sizeof(int)));
+    int bad = 0;
+    e = hipMemsetAsync(tmp, 0, sizeof(int), c->stream);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(dg2k::check_nonneg_kernel, dim3(blocks), dim3(256), 0, c->stream, manning,
+                         (long long)c->n, static_cast<int*>(tmp));
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, tmp, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && bad) {
+      (void)hipFree(tmp);
+      return fail(c, DG2_E_ARG, "bad Manning n (negative or not finite)");
+    }
+  }
   if (e == hipSuccess) {
     if (c->fp32)
-      hipLaunchKernelGGL((dg2k::convert_kernel<float>), dim3(blocks), dim3(256), 0, c->stream, st,
+      hipLaunchKernelGGL((dg2k::convert_kernel<float>), dim3(blocks), dim3(256), 0, c->stream, src,
                          reinterpret_cast<float*>(c->ws + c->L.man), (long long)c->n);
     else
-      hipLaunchKernelGGL((dg2k::convert_kernel<double>), dim3(blocks), dim3(256), 0, c->stream, st,
+      hipLaunchKernelGGL((dg2k::convert_kernel<double>), dim3(blocks), dim3(256), 0, c->stream, src,
                          reinterpret_cast<double*>(c->ws + c->L.man), (long long)c->n);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(st);
+  (void)hipFree(tmp);
   if (e != hipSuccess) return fail(c, DG2_E_DEVICE, "set Manning: %s", hipGetErrorString(e));
+  return DG2_OK;
+}
+
+int dg2_knot_count(const dg2_ctx* c, int32_t seg, int32_t* n_knots) {
+  if (!c || !n_knots || seg < -1 || seg >= (int)c->knot_count.size()) return DG2_E_ARG;
+  int total = 0;
+  for (int s2 = 0; s2 < (int)c->knot_count.size(); ++s2)
+    if (seg < 0 || s2 == seg) total += c->knot_count[s2];
+  *n_knots = total;
   return DG2_OK;
 }
 
@@ -1192,6 +1247,8 @@ struct dg2_tape {
   dg2k::Ctrl* ctrl;            // the tape's own control block for recomputation
   double* ledger;
   double* d_t;                 // the step start times on the device
+  double* man;                 // Manning n per cell as recorded (contexts with a plane)
+  double* knots;               // hydrograph knot table as recorded
   bool recorded;
   std::string err;
 };
@@ -1240,6 +1297,8 @@ Params<double> tape_params(dg2_tape* tp, int r, int k) {
   p.uout = r + 1 < tp->K ? tp->seg + (r + 1) * m9 : nullptr;
   p.ctrl = tp->ctrl;
   p.ledger = tp->ledger;
+  if (p.manning) p.manning = tp->man;  // the parameters the run was recorded with
+  p.knots = tp->knots;
   p.parity = r & 1;
   p.dt_fix = tp->dts[k];
   p.dt_max = 0.0;
@@ -1316,6 +1375,8 @@ int dg2_tape_create(dg2_ctx* c, int32_t n_steps, const double* dts, const int32_
   if (e == hipSuccess) e = hipMalloc((void**)&tp->ctrl, sizeof(dg2k::Ctrl));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->ledger, (size_t)c->L.n_tiles * 4 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&tp->d_t, (size_t)(n_steps + 1) * sizeof(double));
+  if (e == hipSuccess && c->has_manning) e = hipMalloc((void**)&tp->man, c->n * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&tp->knots, 2 * DG2_MAX_KNOTS * sizeof(double));
   if (e == hipSuccess && n_gauges > 0)
     e = hipMemcpyAsync(tp->gidx, gauges, n_gauges * sizeof(int), hipMemcpyHostToDevice, c->stream);
   // the gauges of each cell as a chain in gauge order (the adjoint adds their seeds)
@@ -1337,7 +1398,7 @@ int dg2_tape_create(dg2_ctx* c, int32_t n_steps, const double* dts, const int32_
   return DG2_OK;
 }
 
-int dg2_tape_forward(dg2_tape* tp, double* gauge_h) {
+int dg2_tape_forward(dg2_tape* tp, double* gauge_h, int32_t dst_is_device) {
   if (!tp) return DG2_E_ARG;
   dg2_ctx* c = tp->c;
   const size_t st = 9 * c->n * sizeof(double);
@@ -1347,6 +1408,12 @@ int dg2_tape_forward(dg2_tape* tp, double* gauge_h) {
   tp->t[0] = c->h_ctrl->t[c->parity];
   for (int k = 0; k < tp->n_steps; ++k) tp->t[k + 1] = tp->t[k] + tp->dts[k];
   THIPC(tp, hipMemcpyAsync(tp->d_t, tp->t.data(), tp->t.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  // the parameters of this run: the backward pass recomputes and reverses with these,
+  // whatever the context holds by then
+  if (tp->man)
+    THIPC(tp, hipMemcpyAsync(tp->man, c->ws + c->L.man, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  THIPC(tp, hipMemcpyAsync(tp->knots, c->ws + c->L.knots, 2 * DG2_MAX_KNOTS * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->stream));
   const unsigned gb = (unsigned)((tp->ng + 63) / 64);
   auto cur = [&]() { return reinterpret_cast<double*>(c->ws + (c->parity ? c->L.u1 : c->L.u0)); };
   if (tp->ng > 0) hipLaunchKernelGGL(dg2k::gauge_read_kernel, dim3(gb), dim3(64), 0, c->stream, cur(), tp->gidx, tp->ng, tp->gh);
@@ -1364,14 +1431,17 @@ int dg2_tape_forward(dg2_tape* tp, double* gauge_h) {
   THIPC(tp, hipGetLastError());
   if ((rc = pull_ctrl(c))) return tfail(tp, rc, "%s", c->err.c_str());
   if ((rc = check_health(c))) return tfail(tp, rc, "%s", c->err.c_str());
-  if (gauge_h && tp->ng > 0)
-    THIPC(tp, hipMemcpy(gauge_h, tp->gh, (size_t)(tp->n_steps + 1) * tp->ng * sizeof(double), hipMemcpyDeviceToHost));
+  if (gauge_h && tp->ng > 0) {
+    THIPC(tp, hipMemcpyAsync(gauge_h, tp->gh, (size_t)(tp->n_steps + 1) * tp->ng * sizeof(double),
+                             dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    THIPC(tp, hipStreamSynchronize(c->stream));
+  }
   tp->recorded = true;
   return DG2_OK;
 }
 
 int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, double* grad_q,
-                      double* grad_u0) {
+                      double* grad_u0, int32_t device_ptrs) {
   if (!tp || (tp->ng > 0 && !dj_dh)) return DG2_E_ARG;
   if (!tp->recorded) return tfail(tp, DG2_E_STATE, "no forward run recorded");
   dg2_ctx* c = tp->c;
@@ -1398,7 +1468,7 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
   THIPC(tp, hipMemsetAsync(tp->regime, 0, sizeof(int), sm));
   if (tp->ng > 0) {
     THIPC(tp, hipMemcpyAsync(tp->dj, dj_dh, (size_t)(tp->n_steps + 1) * tp->ng * sizeof(double),
-                             hipMemcpyHostToDevice, sm));
+                             device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, sm));
     hipLaunchKernelGGL(dg2k::gauge_seed_kernel, dim3(gb), dim3(64), 0, sm, tp->lam, tp->gidx, tp->ng,
                        tp->dj + (size_t)tp->n_steps * tp->ng);
   }
@@ -1413,6 +1483,8 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
       const size_t r = (size_t)(k - s0) * m9;
       const double dt = tp->dts[k];
       Params<double> p = params<double>(c);
+      if (p.manning) p.manning = tp->man;  // the recorded parameters
+      p.knots = tp->knots;
       // stage 2: nu2 = lam / 2 + (dL/dV)(U^int)^T (dt lam / 2)
       dg2k::AdjArgs a2{tp->segI + r, tp->lam, 0.5 * dt, tp->t[k] + dt, tp->lam, 0.5, nullptr,
                        nullptr, 0.0, nullptr, nullptr, nullptr, nullptr,
@@ -1437,8 +1509,10 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
   if (regime)
     return tfail(tp, DG2_E_UNSUPPORTED, "the run leaves the adjoint's regime (%s%s)",
                  (regime & 1) ? "a dry cell or face" : "", (regime & 2) ? " a binding velocity cap" : "");
-  if (grad_manning) THIPC(tp, hipMemcpy(grad_manning, tp->gman, c->n * sizeof(double), hipMemcpyDeviceToHost));
-  if (grad_u0) THIPC(tp, hipMemcpy(grad_u0, tp->lam, st, hipMemcpyDeviceToHost));
+  const hipMemcpyKind out_kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (grad_manning) THIPC(tp, hipMemcpyAsync(grad_manning, tp->gman, c->n * sizeof(double), out_kind, sm));
+  if (grad_u0) THIPC(tp, hipMemcpyAsync(grad_u0, tp->lam, st, out_kind, sm));
+  THIPC(tp, hipStreamSynchronize(sm));
   if (grad_q && nseg > 0) {
     std::vector<double> gqf((size_t)tp->n_steps * 2 * nfs);
     THIPC(tp, hipMemcpy(gqf.data(), tp->gq, gqf.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -1453,7 +1527,7 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
       }
     // knots of every inflow segment (host copy of the device table)
     std::vector<double> kn(2 * DG2_MAX_KNOTS);
-    THIPC(tp, hipMemcpy(kn.data(), c->ws + c->L.knots, kn.size() * sizeof(double), hipMemcpyDeviceToHost));
+    THIPC(tp, hipMemcpy(kn.data(), tp->knots, kn.size() * sizeof(double), hipMemcpyDeviceToHost));
     int k0 = 0, out0 = 0;
     for (int sg = 0; sg < nseg; ++sg) {
       const int nk = c->knot_count[sg];
@@ -1487,7 +1561,8 @@ void dg2_tape_destroy(dg2_tape* tp) {
   (void)hipStreamSynchronize(tp->c->stream);
   for (void* b : {(void*)tp->ckpt, (void*)tp->seg, (void*)tp->segV, (void*)tp->segI, (void*)tp->lam,
                   (void*)tp->nu2, (void*)tp->gman, (void*)tp->gq, (void*)tp->gh, (void*)tp->dj, (void*)tp->gidx, (void*)tp->gmap, (void*)tp->gnext,
-                  (void*)tp->regime, (void*)tp->ctrl, (void*)tp->ledger, (void*)tp->d_t})
+                  (void*)tp->regime, (void*)tp->ctrl, (void*)tp->ledger, (void*)tp->d_t,
+                  (void*)tp->man, (void*)tp->knots})
     if (b) (void)hipFree(b);
   delete tp;
 }
@@ -1511,3 +1586,4 @@ void dg2_destroy(dg2_ctx* c) {
 }
 
 }  // extern "C"
+

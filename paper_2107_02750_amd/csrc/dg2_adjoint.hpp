@@ -261,10 +261,11 @@ union AdjSmem {
 };
 
 // One face of the adjoint: the cotangent of the face's stored flux (from mu of the cells
-// on both sides) goes back through the HLL flux, the ghost state (boundary faces) and
-// the revision to the face limits (h, qx, qy) of the cells on both sides: lo for the
-// low cell (its high limit), hi for the high cell (its low limit). A boundary face has
-// one cell; the ghost's cotangent is folded into it.
+// on both sides) goes back through the HLL flux (at an inflow face: the inflow state's
+// own flux), the ghost state (boundary faces) and the revision to the face limits
+// (h, qx, qy) of the cells on both sides: lo for the low cell (its high limit), hi for
+// the high cell (its low limit). A boundary face has one cell; the ghost's cotangent is
+// folded into it.
 struct AdjFace {
   bool xdir;
   int posL, posR;     // box positions of the low and high cells
@@ -348,7 +349,16 @@ __device__ __forceinline__ void adj_face(const Params<double>& p, const AdjArgs&
   // in the normal frame: [mass, normal momentum, tangential momentum]
   const double fb[3] = {mt[0], xdir ? mt[1] : mt[2], xdir ? mt[2] : mt[1]};
   NSide Lb, Rb;
-  hll_rev(g, sL, sR, fb, Lb, Rb);
+  if (kind == 3) {  // an inflow face carries the inflow state's own physical flux
+    const bool high = !F.realR;
+    const NSide gs = high ? sR : sL;
+    const NSide gb{fb[0] * gs.un + fb[1] * (gs.un * gs.un + g * gs.h) + fb[2] * gs.un * gs.ut,
+                   (fb[0] + 2.0 * fb[1] * gs.un + fb[2] * gs.ut) * gs.h, fb[2] * gs.h * gs.un};
+    Lb = high ? NSide{0.0, 0.0, 0.0} : gb;
+    Rb = high ? gb : NSide{0.0, 0.0, 0.0};
+  } else {
+    hll_rev(g, sL, sR, fb, Lb, Rb);
+  }
   if (kind >= 0) {
     const bool high = !F.realR;
     NSide& ob = high ? Lb : Rb;        // the cell's cotangent

@@ -323,6 +323,17 @@ __device__ __forceinline__ void hll(R g, R hL, R unL, R utL, R hR, R unR, R utR,
   f[2] = dry ? R(0) : (up ? FL2 : (dn ? FR2 : S2));
 }
 
+// physical flux of a state (h, un, ut) through a face with normal n:
+// [h un, h un^2 + g h^2 / 2, h un ut]; an inflow face carries its inflow state's own
+// flux (instead of HLL with the interior side), so the segment lets in exactly Q(t)
+template <typename R>
+__device__ __forceinline__ void phys_flux(R g, R h, R un, R ut, R f[3]) {
+  const R q = h * un;
+  f[0] = q;
+  f[1] = q * un + R(0.5) * g * h * h;
+  f[2] = q * ut;
+}
+
 // physical flux along a normal at a Gauss point, velocities zero at or below h_tol
 template <typename R>
 __device__ __forceinline__ void gauss_flux(R g, R ht, R h, R qn, R qt, R f[3]) {
@@ -727,12 +738,24 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   }
   __syncthreads();
   for (int r = tid; r < RB; r += NT) {  // bed means of the box cells (eq 8, diagonal pairs)
-    int i = i0 - 2 + r % RX, j = j0 - 2 + r / RX;
+    const int iu = i0 - 2 + r % RX, ju = j0 - 2 + r / RX;
+    int i = iu, j = ju;
     if (EDGE) {
       i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
       j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
     }
-    sm.z0[r] = R(0.25) * ((zb(i + 1, j + 1) + zb(i, j)) + (zb(i, j + 1) + zb(i + 1, j)));
+    R z = R(0.25) * ((zb(i + 1, j + 1) + zb(i, j)) + (zb(i, j + 1) + zb(i + 1, j)));
+    if (EDGE) {  // beyond an edge (the limiter's ghost): the edge cell's bed plane
+      if (iu != i) {  // continued one cell out; its depth is the edge cell's (clamped)
+        const R dzx = R(0.5) * (zb(i + 1, j + 1) + zb(i + 1, j)) - R(0.5) * (zb(i, j + 1) + zb(i, j));
+        z = iu < i ? z - dzx : z + dzx;
+      }
+      if (ju != j) {
+        const R dzy = R(0.5) * (zb(i, j + 1) + zb(i + 1, j + 1)) - R(0.5) * (zb(i, j) + zb(i + 1, j));
+        z = ju < j ? z - dzy : z + dzy;
+      }
+    }
+    sm.z0[r] = z;
   }
   __syncthreads();
 
@@ -971,13 +994,21 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
       if (!have_r) return;
       rh = own_r.h; ru = own_r.u; rv = own_r.v;
     }
+    int kind = -1;
     if (EDGE && f == 0) {
+      kind = p.bface[j] & 255;
       ghost(p, p.bface[j], t_stage, true, R(1), rh, ru, rv, lh, lu, lv);
     } else if (EDGE && f == nx) {
+      kind = p.bface[ny + j] & 255;
       ghost(p, p.bface[ny + j], t_stage, true, R(-1), lh, lu, lv, rh, ru, rv);
     }
     R out[3];
-    hll(g, lh, lu, lv, rh, ru, rv, out);
+    if (EDGE && kind == 3) {
+      if (f == 0) phys_flux(g, lh, lu, lv, out);
+      else phys_flux(g, rh, ru, rv, out);
+    } else {
+      hll(g, lh, lu, lv, rh, ru, rv, out);
+    }
     sm.fx[0][slot] = out[0];
     sm.fx[1][slot] = out[1];
     sm.fx[2][slot] = out[2];
@@ -1001,13 +1032,21 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
       if (!have_r) return;
       rh = own_r.h; ru = own_r.v; rv = own_r.u;
     }
+    int kind = -1;
     if (EDGE && f == 0) {
+      kind = p.bface[2 * ny + i] & 255;
       ghost(p, p.bface[2 * ny + i], t_stage, false, R(1), rh, ru, rv, lh, lu, lv);
     } else if (EDGE && f == ny) {
+      kind = p.bface[2 * ny + nx + i] & 255;
       ghost(p, p.bface[2 * ny + nx + i], t_stage, false, R(-1), lh, lu, lv, rh, ru, rv);
     }
     R o[3];
-    hll(g, lh, lu, lv, rh, ru, rv, o);
+    if (EDGE && kind == 3) {
+      if (f == 0) phys_flux(g, lh, lu, lv, o);
+      else phys_flux(g, rh, ru, rv, o);
+    } else {
+      hll(g, lh, lu, lv, rh, ru, rv, o);
+    }
     sm.fy[0][slot] = o[0];
     sm.fy[1][slot] = o[2];  // x-momentum is tangential on a y-face
     sm.fy[2][slot] = o[1];
@@ -1372,10 +1411,21 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     R nl = xdir ? sm.u[rl] : sm.v[rl], tl = xdir ? sm.v[rl] : sm.u[rl];
     R nr = xdir ? sm.u[rr_] : sm.v[rr_], tr = xdir ? sm.v[rr_] : sm.u[rr_];
     const int eo = xdir ? 0 : 2 * ny;
-    if (EDGE && f == 0) ghost(p, p.bface[eo + line], t, xdir, R(1), hr, nr, tr, hl, nl, tl);
-    else if (EDGE && f == nf) ghost(p, p.bface[eo + (xdir ? ny : nx) + line], t, xdir, R(-1), hl, nl, tl, hr, nr, tr);
+    int kind = -1;
+    if (EDGE && f == 0) {
+      kind = p.bface[eo + line] & 255;
+      ghost(p, p.bface[eo + line], t, xdir, R(1), hr, nr, tr, hl, nl, tl);
+    } else if (EDGE && f == nf) {
+      kind = p.bface[eo + (xdir ? ny : nx) + line] & 255;
+      ghost(p, p.bface[eo + (xdir ? ny : nx) + line], t, xdir, R(-1), hl, nl, tl, hr, nr, tr);
+    }
     R o3[3];
-    hll(g, hl, nl, tl, hr, nr, tr, o3);
+    if (EDGE && kind == 3) {
+      if (f == 0) phys_flux(g, hl, nl, tl, o3);
+      else phys_flux(g, hr, nr, tr, o3);
+    } else {
+      hll(g, hl, nl, tl, hr, nr, tr, o3);
+    }
     sm.f[0][r] = o3[0];
     sm.f[1][r] = xdir ? o3[1] : o3[2];  // x-momentum is tangential on a y-face
     sm.f[2][r] = xdir ? o3[2] : o3[1];
@@ -1508,6 +1558,16 @@ template <typename R>
 __global__ void convert_kernel(const double* __restrict__ src, R* __restrict__ dst, long long count) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < count) dst[k] = R(src[k]);
+}
+
+// sets *bad when any of count values is negative or not finite (Manning n given in
+// device memory is checked before it replaces the plane)
+__global__ void check_nonneg_kernel(const double* __restrict__ src, long long count, int* bad) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) {
+    const double v = src[k];
+    if (!(v >= 0.0) || !(v <= 1.7976931348623157e308)) atomicOr(bad, 1);
+  }
 }
 
 // initial coefficients (Sect. 2.1.4) from the staged double input

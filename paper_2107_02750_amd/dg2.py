@@ -25,7 +25,8 @@ SYMBOLS = ("dg2_workspace_size", "dg2_init", "dg2_step", "dg2_run", "dg2_read",
            "dg2_bed_info", "dg2_plan_bed_datum", "dg2_tile_shapes", "dg2_tile_grid",
            "dg2_batch_create",
            "dg2_batch_step", "dg2_batch_run", "dg2_batch_last_error", "dg2_batch_destroy",
-           "dg2_set_manning", "dg2_set_hydrograph", "dg2_tape_create", "dg2_tape_forward",
+           "dg2_set_manning", "dg2_set_hydrograph", "dg2_knot_count", "dg2_tape_create",
+           "dg2_tape_forward",
            "dg2_tape_backward", "dg2_tape_last_error", "dg2_tape_destroy",
            "dg2_last_error", "dg2_init_error", "dg2_destroy")
 
@@ -99,11 +100,12 @@ def load(path: str = LIB_PATH):
     lib.dg2_batch_last_error.restype = C.c_char_p
     lib.dg2_batch_destroy.argtypes = [vp]
     lib.dg2_batch_destroy.restype = None
-    lib.dg2_set_manning.argtypes = [vp, _dp]
+    lib.dg2_set_manning.argtypes = [vp, vp, i32]
     lib.dg2_set_hydrograph.argtypes = [vp, i32, _dp]
+    lib.dg2_knot_count.argtypes = [vp, i32, C.POINTER(i32)]
     lib.dg2_tape_create.argtypes = [vp, i32, _dp, C.POINTER(i32), i32, i32, C.POINTER(vp)]
-    lib.dg2_tape_forward.argtypes = [vp, _dp]
-    lib.dg2_tape_backward.argtypes = [vp, _dp, _dp, _dp, _dp]
+    lib.dg2_tape_forward.argtypes = [vp, vp, i32]
+    lib.dg2_tape_backward.argtypes = [vp, vp, vp, _dp, vp, i32]
     lib.dg2_tape_last_error.argtypes = [vp]
     lib.dg2_tape_last_error.restype = C.c_char_p
     lib.dg2_tape_destroy.argtypes = [vp]
@@ -114,6 +116,30 @@ def load(path: str = LIB_PATH):
 
 def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _boundaries(sc):
+    """The boundary segments of a scenario as a C array, their count, and the host
+    arrays the C array points into (to be kept alive while it is used)."""
+    keep = []
+    nb = len(sc.boundaries)
+    arr = (Boundary * max(nb, 1))()
+    for k, b in enumerate(sc.boundaries):
+        tk, qk = _f64(b.t_knots), _f64(b.q_knots)
+        keep += [tk, qk]
+        arr[k] = Boundary(b.edge, b.kind, b.i0, b.i1, 0 if tk is None else len(tk),
+                          _ptr(tk), _ptr(qk), b.h_b, b.u_b, b.v_b)
+    return arr, nb, keep
+
+
+def _is_device_tensor(a) -> bool:
+    return type(a).__module__.startswith("torch") and getattr(a, "is_cuda", False)
+
+
+def _check_device_f64(t, count: int) -> None:
+    import torch
+    if t.dtype != torch.float64 or t.numel() != count:
+        raise DG2Error(E_ARG, f"expected {count} float64 values, got {t.numel()} {t.dtype}")
 
 
 def _ptr(a):
@@ -210,16 +236,9 @@ class DG2:
             raise DG2Error(rc, "bad configuration")
         self.workspace = torch.empty(ws.value, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        keep = []
         zv, man, data = _f64(sc.zv), _f64(sc.manning), _f64(sc.init_data)
+        arr, nb, keep = _boundaries(sc)
         keep += [zv, man, data]
-        nb = len(sc.boundaries)
-        arr = (Boundary * max(nb, 1))()
-        for k, b in enumerate(sc.boundaries):
-            tk, qk = _f64(b.t_knots), _f64(b.q_knots)
-            keep += [tk, qk]
-            arr[k] = Boundary(b.edge, b.kind, b.i0, b.i1, 0 if tk is None else len(tk),
-                              _ptr(tk), _ptr(qk), b.h_b, b.u_b, b.v_b)
         h = C.c_void_p()
         rc = lib.dg2_init(C.byref(cfg), _ptr(zv), _ptr(man), float(sc.manning_scalar),
                           int(sc.init_mode), _ptr(data), float(sc.eta_level), arr, nb,
@@ -304,9 +323,22 @@ class DG2:
         self._check(self._lib.dg2_get_timing(self._h, C.byref(s), C.byref(a), C.byref(b)))
         return dict(steps=s.value, ms_stage1=a.value, ms_stage2=b.value)
 
-    def set_manning(self, manning: np.ndarray) -> None:
+    def set_manning(self, manning) -> None:
+        """Replace the per-cell Manning plane: a host array, or a float64 torch tensor
+        on this simulation's device (used in place, nothing goes through the host)."""
+        if _is_device_tensor(manning):
+            m = manning.detach().contiguous().reshape(-1)
+            _check_device_f64(m, self.ny * self.nx)
+            self._check(self._lib.dg2_set_manning(self._h, C.c_void_p(m.data_ptr()), 1))
+            return
         m = _f64(manning).reshape(-1)
-        self._check(self._lib.dg2_set_manning(self._h, _ptr(m)))
+        self._check(self._lib.dg2_set_manning(self._h, m.ctypes.data_as(C.c_void_p), 0))
+
+    def knot_count(self, seg: int = -1) -> int:
+        """Hydrograph knots of boundary segment seg (-1: all segments together)."""
+        k = C.c_int32()
+        self._check(self._lib.dg2_knot_count(self._h, int(seg), C.byref(k)))
+        return k.value
 
     def set_hydrograph(self, seg: int, q_knots: np.ndarray) -> None:
         q = _f64(q_knots).reshape(-1)
@@ -388,21 +420,45 @@ class Tape:
         if rc != 0:
             raise DG2Error(rc, self._lib.dg2_tape_last_error(self._h).decode())
 
-    def forward(self) -> np.ndarray:
-        """Run the schedule; returns the gauge depths, (n_steps + 1) x n_gauges."""
+    def forward(self, device: bool = False):
+        """Run the schedule; returns the gauge depths, (n_steps + 1) x n_gauges (a numpy
+        array, or with device=True a float64 tensor on the simulation's device)."""
+        if device:
+            import torch
+            out = torch.empty((self.n_steps + 1, max(self.ng, 1)), dtype=torch.float64,
+                              device=self.sim.device)
+            self._check(self._lib.dg2_tape_forward(self._h, C.c_void_p(out.data_ptr()), 1))
+            return out[:, :self.ng]
         out = np.empty((self.n_steps + 1, self.ng))
-        self._check(self._lib.dg2_tape_forward(self._h, _ptr(out)))
+        self._check(self._lib.dg2_tape_forward(self._h, out.ctypes.data_as(C.c_void_p), 0))
         return out
 
-    def backward(self, dj_dh: np.ndarray, n_knots: int):
-        """dJ/d(gauge depths) -> (dJ/dn per cell, dJ/dq per knot, dJ/dU0)."""
-        dj = _f64(dj_dh).reshape(self.n_steps + 1, self.ng)
-        gm = np.empty(self.sim.ny * self.sim.nx)
-        gq = np.empty(max(n_knots, 1))
-        gu = np.empty(9 * self.sim.ny * self.sim.nx)
-        self._check(self._lib.dg2_tape_backward(self._h, _ptr(dj), _ptr(gm), _ptr(gq), _ptr(gu)))
-        return (gm.reshape(self.sim.ny, self.sim.nx), gq[:n_knots],
-                gu.reshape(9, self.sim.ny, self.sim.nx))
+    def backward(self, dj_dh, n_knots: int | None = None):
+        """dJ/d(gauge depths) -> (dJ/dn per cell, dJ/dq per knot, dJ/dU0). dJ/dq covers
+        every knot of every segment in segment order (the first n_knots if given).
+        A float64 device tensor dj_dh keeps dJ/dn and dJ/dU0 on the device (tensors);
+        a host array gives numpy arrays."""
+        nq = self.sim.knot_count(-1)
+        gq = np.zeros(max(nq, 1))
+        ny, nx = self.sim.ny, self.sim.nx
+        if _is_device_tensor(dj_dh):
+            import torch
+            dj = dj_dh.detach().to(torch.float64).contiguous().reshape(-1)
+            _check_device_f64(dj, (self.n_steps + 1) * self.ng)
+            gm = torch.empty(ny * nx, dtype=torch.float64, device=self.sim.device)
+            gu = torch.empty(9 * ny * nx, dtype=torch.float64, device=self.sim.device)
+            self._check(self._lib.dg2_tape_backward(self._h, C.c_void_p(dj.data_ptr()),
+                                                    C.c_void_p(gm.data_ptr()), _ptr(gq),
+                                                    C.c_void_p(gu.data_ptr()), 1))
+        else:
+            dj = _f64(dj_dh).reshape(self.n_steps + 1, self.ng)
+            gm = np.empty(ny * nx)
+            gu = np.empty(9 * ny * nx)
+            self._check(self._lib.dg2_tape_backward(self._h, dj.ctypes.data_as(C.c_void_p),
+                                                    _ptr(gm), _ptr(gq),
+                                                    gu.ctypes.data_as(C.c_void_p), 0))
+        gq = gq[:nq] if n_knots is None else gq[:n_knots]
+        return gm.reshape(ny, nx), gq, gu.reshape(9, ny, nx)
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -425,21 +481,23 @@ def gauge_run_function():
         @staticmethod
         def forward(ctx, manning, q_knots, sim, dts, gauges, state0):
             sim.set_state(state0)
-            sim.set_manning(manning.detach().cpu().numpy())
-            sim.set_hydrograph(0, q_knots.detach().cpu().numpy())
+            sim.set_manning(manning.detach().to(device=sim.device, dtype=torch.float64))
+            sim.set_hydrograph(0, q_knots.detach().cpu().numpy())  # a few knots
             tape = Tape(sim, dts, gauges)
-            gh = tape.forward()
+            gh = tape.forward(device=True)
             ctx.tape = tape
             ctx.n_knots = int(q_knots.numel())
             ctx.shapes = (manning.shape, manning.dtype, manning.device)
-            return torch.as_tensor(gh, dtype=manning.dtype, device=manning.device)
+            return gh.to(dtype=manning.dtype, device=manning.device)
 
         @staticmethod
         def backward(ctx, g):
-            gm, gq, _ = ctx.tape.backward(g.detach().cpu().numpy(), ctx.n_knots)
+            gm, gq, _ = ctx.tape.backward(g.detach().to(device=ctx.tape.sim.device,
+                                                          dtype=torch.float64), ctx.n_knots)
             ctx.tape.close()
             shape, dtype, dev = ctx.shapes
-            return (torch.as_tensor(gm, dtype=dtype, device=dev).reshape(shape),
+            return (gm.to(dtype=dtype, device=dev).reshape(shape),
                     torch.as_tensor(gq, dtype=dtype, device=dev), None, None, None, None)
 
     return GaugeRun
+

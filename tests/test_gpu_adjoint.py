@@ -242,3 +242,69 @@ def test_regime_flag_from_a_partial_tile_edge_face(dg2):
         tape.backward(np.ones_like(hs), len(sc.boundaries[0].q_knots))
     assert e.value.code == dg2.E_UNSUPPORTED
     assert "velocity cap" in str(e.value)
+
+
+def test_two_inflow_segments_give_every_knot_gradient(dg2):
+    """A second inflow segment (south edge, 3 knots) besides the west one (8 knots):
+    dJ/dq comes back for all 11 knots in segment order, each part against the CPU
+    reference."""
+    base = case()
+    t2 = np.array([0.0, 2.0, 4.0])
+    q2 = np.array([5.0, 15.0, 8.0])
+    sc = base.replace(boundaries=base.boundaries + [S.Boundary(S.S, S.INFLOW, 14, 20, t2, q2)])
+    dts = schedule(sc, 15)
+    gi = gauges(N)
+    href = href_of(sc, dts, gi)
+    ref = WetDG2(sc)
+    zi = S.zone_index(N, 4)
+    n_cell = torch.as_tensor(sc.manning)
+    qa = torch.tensor(np.asarray(sc.boundaries[0].q_knots, dtype=np.float64), requires_grad=True)
+    qb = torch.tensor(q2, requires_grad=True)
+    U = torch.tensor(Oracle(sc).planes())
+    t, J = 0.0, 0.0
+    for k, dt in enumerate(dts):
+        U = ref.step(U, float(dt), t, n_cell, [qa, qb])
+        t += float(dt)
+        J = J + ((U[0].reshape(-1)[torch.as_tensor(gi)] - torch.as_tensor(href[k + 1])) ** 2).sum()
+    J.backward()
+    sim = dg2.DG2(sc, dg2.FP64)
+    assert sim.knot_count(0) == 8 and sim.knot_count(1) == 3 and sim.knot_count(-1) == 11
+    tape = dg2.Tape(sim, dts, gi)
+    hs = tape.forward()
+    dj = 2.0 * (hs - href)
+    dj[0] = 0.0                       # the reference's misfit starts after step 1
+    _, gq, _ = tape.backward(dj)
+    assert gq.shape == (11,)
+    want = np.concatenate([qa.grad.numpy(), qb.grad.numpy()])
+    err = np.abs(gq - want).max() / np.abs(want).max()
+    print(f"two inflow segments: knot gradients vs reference {err:.2e}", flush=True)
+    assert err <= 1e-7
+    assert np.abs(qb.grad.numpy()).max() > 0.0
+    del zi
+
+
+def test_backward_uses_the_parameters_it_was_recorded_with(dg2):
+    """Two applies of the autograd Function with different Manning values on the same
+    simulation, then the backward of the first only: its gradient is the one at the
+    first values (the tape keeps the parameters of its own run)."""
+    sc = case()
+    dts = schedule(sc, 12)
+    gi = gauges(N)
+    href = href_of(sc, dts, gi)
+    _, _, gz_ref, _, _ = reference(sc, dts, gi, href)
+    sim = dg2.DG2(sc, dg2.FP64)
+    state0 = sim.get_state()
+    zi = torch.as_tensor(S.zone_index(N, 4), device="cuda")
+    nz0 = np.array([sc.manning.reshape(-1)[S.zone_index(N, 4).reshape(-1) == z][0] for z in range(16)])
+    nz = torch.tensor(nz0, device="cuda", requires_grad=True)
+    other = torch.tensor(1.5 * nz0, device="cuda", requires_grad=True)
+    qk = torch.tensor(np.asarray(sc.boundaries[0].q_knots, dtype=np.float64), device="cuda")
+    f = dg2.gauge_run_function()
+    h1 = f.apply(nz[zi], qk, sim, dts, gi, state0)
+    h2 = f.apply(other[zi], qk, sim, dts, gi, state0)   # leaves the context at 1.5 n
+    assert not torch.equal(h1, h2)
+    ((h1 - torch.as_tensor(href, device="cuda")) ** 2).sum().backward()
+    ez = np.abs(nz.grad.cpu().numpy() - gz_ref).max() / np.abs(gz_ref).max()
+    print(f"backward after a second forward: zones {ez:.2e}", flush=True)
+    assert ez <= 1e-7
+    assert other.grad is None
