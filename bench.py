@@ -5,10 +5,12 @@ Workload: the 1024 x 1024 fractional-Brownian terrain with a carved meandering c
 25 m - z, uniform discharge 2 m^2/s) so that every cell does the full wet-cell work:
 friction, limiting, wet-wet HLL fluxes. A step is one full RK2 time step (friction,
 two stages, CFL time step) over every cell. The state is resident in HBM before the
-timed region starts; K steps are timed between device synchronisations, with nothing
-recorded in between. K further steps, each launch bracketed by HIP events on the launch
-stream, give the kernel durations (an event record costs the stream a few microseconds,
-about 9 % of a step with three per step, so the throughput is taken without them).
+timed region starts; after W warm-up steps, windows of exactly K steps are timed between
+device synchronisations, with nothing recorded in between, until at least 1 s has been
+timed, and the median window gives the rate. Further windows, each launch bracketed by
+HIP events on the launch stream, give the kernel durations (an event record costs the
+stream a few microseconds, about 9 % of a step with three per step, so the throughput
+is taken without them).
 
 Also reported, on the same line: the FP32 instantiation on the same workload with its
 depth error against the FP64 path, the same terrain as configured (dry start, channel
@@ -50,11 +52,13 @@ def stage_bytes(stage, n_cells, real_bytes, table=ALG_VALUES):
 
 
 def kernel_source_hash():
-    """sha256 of what the forward kernels are compiled from: their source and the
-    build script that holds the compiler flags."""
+    """sha256 of what the forward kernels are compiled from and launched by: their
+    source, the host library that sets their launch geometry, and the build script
+    that holds the compiler flags."""
     import hashlib
     h = hashlib.sha256()
     for f in (os.path.join(ROOT, "paper_2107_02750_amd", "csrc", "dg2_kernels.hpp"),
+              os.path.join(ROOT, "paper_2107_02750_amd", "csrc", "dg2.hip"),
               os.path.join(ROOT, "paper_2107_02750_amd", "build.py")):
         with open(f, "rb") as fh:
             h.update(fh.read())
@@ -80,45 +84,68 @@ def measured_traffic(summary, kernel):
     return 1024.0 * (k["fetch"] * sc["fetch"] + k["write"] * sc["write"])
 
 
-def timed_steps(sim, steps):
-    """Wall time of `steps` steps between two device synchronisations, with nothing
-    recorded in between, then the mean stage-kernel durations from HIP events on the
-    launch stream over `steps` further steps with every launch bracketed (an event
+def timed_steps(sim, steps, min_seconds=1.0, min_windows=5, event_seconds=0.25):
+    """Throughput and kernel durations of a simulation.
+
+    Throughput: windows of exactly `steps` steps, each between two device
+    synchronisations with nothing recorded inside, repeated until at least min_seconds
+    have been timed and at least min_windows windows run; returns the median window's
+    wall time (robust to clock ramp-up and stray host delays) and the window count.
+    Kernel durations: the mean stage-kernel times from HIP events on the launch stream
+    over further windows with every launch bracketed (at least event_seconds; an event
     record costs the stream a few microseconds, which the throughput leaves out)."""
     import torch
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        sim.step(sync=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    wins = []
+    while sum(wins) < min_seconds or len(wins) < min_windows:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sim.step(sync=False)
+        torch.cuda.synchronize()
+        wins.append(time.perf_counter() - t0)
     sim.set_timing(True)
-    for _ in range(steps):
-        sim.step(sync=False)
+    t_ev = 0.0
+    while t_ev < event_seconds:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sim.step(sync=False)
+        torch.cuda.synchronize()
+        t_ev += time.perf_counter() - t0
     tm = sim.timing()
     sim.set_timing(False)
-    return t1 - t0, tm
+    return float(np.median(wins)), tm, len(wins)
 
 
 def cpu_baseline(sc, budget_s):
     """The FP64 CPU oracle on this host, stepping the same workload until budget_s
-    seconds have passed (at least one step) after two untimed steps."""
+    seconds have passed (at least one step) after two untimed steps, on all the
+    threads OpenMP gives it; then the same on one thread for half that budget."""
     import oracle
+
+    def rate(o, budget):
+        t1 = time.perf_counter()
+        steps = 0
+        while True:
+            o.step()
+            steps += 1
+            secs = time.perf_counter() - t1
+            if secs >= budget:
+                return steps, secs
+
     o = oracle.Oracle(sc)
     o.step()  # the first two steps also start the threads and touch both state buffers
     o.step()
-    t1 = time.perf_counter()
-    steps = 0
-    while True:
-        o.step()
-        steps += 1
-        secs = time.perf_counter() - t1
-        if secs >= budget_s:
-            break
+    cores = oracle.threads()
+    steps, secs = rate(o, budget_s)
+    oracle.set_threads(1)
+    steps1, secs1 = rate(o, 0.5 * budget_s)
+    oracle.set_threads(cores)
     return dict(value=sc.nx * sc.ny * steps / secs, unit="cell-updates/s",
-                cores=oracle.threads(), kind="oracle",
+                cores=cores, kind="oracle",
                 sample=f"{steps} FP64 oracle steps of the same {sc.nx}x{sc.ny} all-wet "
-                       f"workload ({secs:.1f} s)")
+                       f"workload ({secs:.1f} s)",
+                one_core={"value": sc.nx * sc.ny * steps1 / secs1, "cores": 1,
+                          "sample": f"{steps1} further steps on one thread ({secs1:.1f} s)"})
 
 
 def fv1_leg(dg2, S, n, steps, warmup):
@@ -133,7 +160,7 @@ def fv1_leg(dg2, S, n, steps, warmup):
         for _ in range(warmup):
             sim.step(sync=False)
         torch.cuda.synchronize()
-        el, tm = timed_steps(sim, steps)
+        el, tm, _ = timed_steps(sim, steps)
         ms = tm["ms_stage1"]
         bytes_ = 7 * rb * n * n
         out[tag] = {"value": n * n * steps / el, "unit": "cell-updates/s", "ms_per_launch": ms,
@@ -179,9 +206,11 @@ def adjoint_leg(dg2, S, n, steps, n_gauges=32):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for dt in dts:
-        plain.step(dt_max=float(dt), sync=False)
+        plain.step(dt_max=float(dt), sync=False)   # each step is capped at dts[k]
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    # the same schedule as the tape (the CFL step never fell below dts[k])
+    assert abs(plain.scalars()["t"] - float(np.sum(dts))) <= 1e-9 * float(np.sum(dts))
     sim, tape, h, t_fwd = run()
     J = float(((h - href) ** 2).sum())
     t0 = time.perf_counter()
@@ -213,6 +242,7 @@ def adjoint_leg(dg2, S, n, steps, n_gauges=32):
             "misfit": J, "checkpoint_every": int(np.ceil(np.sqrt(steps))),
             "seconds": {"forward_plain": t_plain, "forward_recorded": t_fwd, "adjoint": t_bwd},
             "adjoint_over_forward": t_bwd / t_plain,
+            "gradient_over_forward": (t_fwd + t_bwd) / t_plain,
             "fd_checks": checks, "max_rel_diff_vs_fd": worst}
 
 
@@ -264,7 +294,10 @@ def precision_form(dg2, S, n, t_end):
                      "rms_depth_error_m": float(np.sqrt(np.mean(d * d))),
                      "bed_quantum_m": sim.bed_info()["quantum"]}
     res["bed_plus_1000m"] = elev
-    res["error_vs"] = "the FP64 GPU run on the same bed (which matches the FP64 oracle to 1e-12)"
+    res["error_vs"] = ("the FP64 GPU run on the same bed; the parity tests hold that run to the "
+                       "FP64 oracle at 1e-12 on a 2048x512 window of this terrain (100 steps from "
+                       "the oracle's state at t=300 s) and check the FP32 path against the oracle "
+                       "on it")
     return res
 
 
@@ -372,7 +405,7 @@ def main():
     for _ in range(args.warmup):
         sim.step(sync=False)
     torch.cuda.synchronize()
-    el, tm = timed_steps(sim, args.steps)
+    el, tm, n_windows = timed_steps(sim, args.steps)
     value = n_cells * args.steps / el
     ms1, ms2 = tm["ms_stage1"], tm["ms_stage2"]
     dom, dom_ms = ("stage2", ms2) if ms2 >= ms1 else ("stage1", ms1)
@@ -406,7 +439,9 @@ def main():
         "config": {"workload": f"fbm+channel terrain {sc.nx}x{sc.ny}, dx=5 m, n=0.035, "
                                "flooded to 25 m with qx=2 m^2/s (every cell wet)",
                    "cells": n_cells, "tile": [info["tile_x"], info["tile_y"]],
-                   "blocks_per_launch": info["blocks"]},
+                   "blocks_per_launch": info["blocks"],
+                   "timing": f"median of {n_windows} windows of {args.steps} steps "
+                             f"(at least 1 s timed in all)", "windows": n_windows},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(
@@ -424,7 +459,7 @@ def main():
         for _ in range(args.warmup):
             s32.step(sync=False)
         torch.cuda.synchronize()
-        el32, tm32 = timed_steps(s32, args.steps)
+        el32, tm32, _ = timed_steps(s32, args.steps)
         a64, a32 = dg2.DG2(sc, dg2.FP64), dg2.DG2(sc, dg2.FP32)
         a64.run(60.0)
         a32.run(60.0)
@@ -437,7 +472,7 @@ def main():
                        / ((tm32["ms_stage1"] + tm32["ms_stage2"]) * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "max_depth_error_m": float(np.abs(d).max()),
                        "rms_depth_error_m": float(np.sqrt(np.mean(d * d))),
-                       "error_at": "t=60 s vs the FP64 GPU path (which matches the FP64 oracle to 1e-12)"}
+                       "error_at": "t=60 s vs the FP64 GPU path (held to the FP64 oracle at 1e-12 by the parity tests)"}
         print(f"[bench] FP32 {out['fp32']['value']:.4g} cell-updates/s, max depth err "
               f"{out['fp32']['max_depth_error_m']:.3g} m", file=sys.stderr, flush=True)
         # the terrain as configured: dry start, inflow hydrograph, snapshot at t = 3600 s
@@ -447,7 +482,7 @@ def main():
         spin = sd.run(3600.0)
         spin_s = time.perf_counter() - t0
         wet = float((sd.read(0) > dry.h_tol).mean())
-        eld, _ = timed_steps(sd, args.steps)
+        eld, _, _ = timed_steps(sd, args.steps)
         out["as_configured"] = {"workload": "same terrain, dry start, 50 m^3/s trapezoid inflow, "
                                             "timed from the state at t=3600 s",
                                 "value": n_cells * args.steps / eld, "wet_fraction": wet,

@@ -72,6 +72,8 @@ def load():
     lib.dg2ref_operator.argtypes = [vp, _dp, C.c_double, _dp, _dp, _dp]
     lib.dg2ref_threads.argtypes = []
     lib.dg2ref_threads.restype = C.c_int
+    lib.dg2ref_set_threads.argtypes = [C.c_int]
+    lib.dg2ref_set_threads.restype = None
     lib.dg2ref_limit.argtypes = [vp, _dp, _dp]
     lib.dg2ref_friction.argtypes = [vp, _dp, C.c_double, _dp]
     _lib = lib
@@ -220,3 +222,8 @@ def bed_coeffs(zv: np.ndarray):
 def threads() -> int:
     """OpenMP threads the oracle's passes run on."""
     return int(load().dg2ref_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's passes on n OpenMP threads (from the calling thread on)."""
+    load().dg2ref_set_threads(int(n))

@@ -61,6 +61,7 @@ struct dg2ref_ctx {
   double *U;              /* 9 planes: the state U^n */
   double *F, *V, *Ui, *W, *L; /* work planes */
   unsigned char *flat;    /* per cell: 1 if the limited stage input is locally first order */
+  double *rowsum;         /* per row: partial sums of a pass */
   face_t *xf;             /* (nx+1)*ny x-faces, face f of row j at j*(nx+1)+f */
   face_t *yf;             /* nx*(ny+1) y-faces, face f of column i at f*nx+i */
   bface_t *bw, *be, *bs, *bn; /* boundary face kinds */
@@ -639,23 +640,31 @@ int dg2ref_operator(dg2ref_ctx *c, const double *state, double t, double *L,
  * added is booked as clip mass), and a cell with h0 <= h_tol loses its discharge. */
 static double pass_cleanup(dg2ref_ctx *c, double *S, int *bad) {
   const size_t n = c->n;
+  const int nx = c->nx, ny = c->ny;
   const double area = c->cfg.dx * c->cfg.dx, ht = c->cfg.h_tol;
-  double clip = 0.0;
   int nan_seen = 0;
-  for (size_t k = 0; k < n; ++k) {
-    for (int p = 0; p < 9; ++p)
-      if (isnan(S[p * n + k])) nan_seen = 1;
-    double h0 = S[PL(0, 0) * n + k];
-    if (h0 < 0.0) {
-      clip += -h0 * area;
-      S[PL(0, 0) * n + k] = 0.0;
-      S[PL(0, 1) * n + k] = 0.0;
-      S[PL(0, 2) * n + k] = 0.0;
-      h0 = 0.0;
+#pragma omp parallel for schedule(static) reduction(| : nan_seen)
+  for (int j = 0; j < ny; ++j) {
+    double clip = 0.0; /* the clipped mass of row j, summed along the row */
+    for (int i = 0; i < nx; ++i) {
+      size_t k = (size_t)j * nx + i;
+      for (int p = 0; p < 9; ++p)
+        if (isnan(S[p * n + k])) nan_seen |= 1;
+      double h0 = S[PL(0, 0) * n + k];
+      if (h0 < 0.0) {
+        clip += -h0 * area;
+        S[PL(0, 0) * n + k] = 0.0;
+        S[PL(0, 1) * n + k] = 0.0;
+        S[PL(0, 2) * n + k] = 0.0;
+        h0 = 0.0;
+      }
+      if (h0 <= ht)
+        for (int p = 3; p < 9; ++p) S[p * n + k] = 0.0;
     }
-    if (h0 <= ht)
-      for (int p = 3; p < 9; ++p) S[p * n + k] = 0.0;
+    c->rowsum[j] = clip;
   }
+  double clip = 0.0; /* rows in order: the same sum on any number of threads */
+  for (int j = 0; j < ny; ++j) clip += c->rowsum[j];
   *bad = nan_seen;
   return clip;
 }
@@ -672,6 +681,7 @@ static double cfl_dt(const dg2ref_ctx *c, const double *S, double t) {
   const size_t n = c->n;
   const double g = c->cfg.g, ht = c->cfg.h_tol, dx = c->cfg.dx;
   double m = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : m)
   for (size_t k = 0; k < n; ++k) {
     double h0 = S[PL(0, 0) * n + k];
     if (!(h0 > ht)) continue;
@@ -728,11 +738,13 @@ static int do_step(dg2ref_ctx *c, double dt_max, double t_end, double *dt_used) 
   int bad1 = 0, bad2 = 0;
   pass_faces(c, c->V, c->t, &in1, &out1);
   pass_operator(c, c->L);
+#pragma omp parallel for schedule(static)
   for (size_t m = 0; m < 9 * n; ++m) c->Ui[m] = c->V[m] + dt * c->L[m];
   double clip1 = pass_cleanup(c, c->Ui, &bad1);
   pass_limit(c, c->Ui, c->W);
   pass_faces(c, c->W, t_next, &in2, &out2);
   pass_operator(c, c->L);
+#pragma omp parallel for schedule(static)
   for (size_t m = 0; m < 9 * n; ++m) c->U[m] = 0.5 * (c->V[m] + c->W[m] + dt * c->L[m]);
   double clip2 = pass_cleanup(c, c->U, &bad2);
   c->mass_in += 0.5 * dt * (in1 + in2);
@@ -762,6 +774,7 @@ static void fv1_faces(dg2ref_ctx *c, const double *S, double t, double *in_rate,
   const size_t n = c->n;
   const double g = c->cfg.g, ht = c->cfg.h_tol;
   const double *h = S + PL(0, 0) * n, *qx = S + PL(1, 0) * n, *qy = S + PL(2, 0) * n;
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int f = 0; f <= nx; ++f) {
       face_t *fc = &c->xf[(size_t)j * (nx + 1) + f];
@@ -786,6 +799,7 @@ static void fv1_faces(dg2ref_ctx *c, const double *S, double t, double *in_rate,
       else
         dg2ref_hll(g, fc->lo.h, fc->lo.u, fc->lo.v, fc->hi.h, fc->hi.u, fc->hi.v, fc->flux);
     }
+#pragma omp parallel for schedule(static)
   for (int f = 0; f <= ny; ++f)
     for (int i = 0; i < nx; ++i) {
       face_t *fc = &c->yf[(size_t)f * nx + i];
@@ -846,6 +860,7 @@ static int do_step_fv1(dg2ref_ctx *c, double dt_max, double t_end, double *dt_us
   if (!(dt > 0.0)) return fail(c, DG2REF_E_NUMERIC, "non-positive time step %g at t=%g", dt, c->t);
   /* friction at the centre: F = U with q replaced by the friction update */
   memcpy(c->F, c->U, 9 * n * sizeof(double));
+#pragma omp parallel for schedule(static)
   for (size_t k = 0; k < n; ++k) {
     double q[2];
     dg2ref_friction_point(g, c->manning[k], ht, dt, c->U[PL(0, 0) * n + k],
@@ -856,6 +871,7 @@ static int do_step_fv1(dg2ref_ctx *c, double dt_max, double t_end, double *dt_us
   double in, out;
   fv1_faces(c, c->F, c->t, &in, &out);
   /* eq 7 with L0: flux differences and the bed source of each direction */
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       size_t k = (size_t)j * nx + i;
@@ -918,7 +934,7 @@ static int edge_len(const dg2ref_ctx *c, int edge) { return edge <= DG2REF_E ? c
 void dg2ref_destroy(dg2ref_ctx *c) {
   if (!c) return;
   free(c->zv); free(c->z0); free(c->z1x); free(c->z1y); free(c->manning);
-  free(c->U); free(c->F); free(c->V); free(c->Ui); free(c->W); free(c->L); free(c->flat);
+  free(c->U); free(c->F); free(c->V); free(c->Ui); free(c->W); free(c->L); free(c->flat); free(c->rowsum);
   free(c->xf); free(c->yf); free(c->bw); free(c->be); free(c->bs); free(c->bn);
   if (c->segs)
     for (int s = 0; s < c->n_segs; ++s) { free(c->segs[s].t_knots); free(c->segs[s].q_knots); }
@@ -972,6 +988,7 @@ int dg2ref_init(const dg2ref_config *cfg, const double *zv, const double *mannin
   c->W = calloc(9 * n, sizeof(double));
   c->L = calloc(9 * n, sizeof(double));
   c->flat = calloc(n, 1);
+  c->rowsum = calloc(cfg->ny, sizeof(double));
   c->xf = calloc((size_t)(cfg->nx + 1) * cfg->ny, sizeof(face_t));
   c->yf = calloc((size_t)cfg->nx * (cfg->ny + 1), sizeof(face_t));
   c->bw = calloc(cfg->ny, sizeof(bface_t));
@@ -980,7 +997,7 @@ int dg2ref_init(const dg2ref_config *cfg, const double *zv, const double *mannin
   c->bn = calloc(cfg->nx, sizeof(bface_t));
   c->segs = calloc(n_bcs > 0 ? n_bcs : 1, sizeof(seg_t));
   if (!c->zv || !c->z0 || !c->z1x || !c->z1y || !c->manning || !c->U || !c->F || !c->V ||
-      !c->Ui || !c->W || !c->L || !c->flat || !c->xf || !c->yf || !c->bw || !c->be || !c->bs || !c->bn ||
+      !c->Ui || !c->W || !c->L || !c->flat || !c->rowsum || !c->xf || !c->yf || !c->bw || !c->be || !c->bs || !c->bn ||
       !c->segs)
     BAD("out of host memory");
   memcpy(c->zv, zv, nv * sizeof(double));
@@ -1152,5 +1169,13 @@ int dg2ref_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+
+void dg2ref_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
 #endif
 }

@@ -88,8 +88,9 @@ const char *dg2ref_last_error(const dg2ref_ctx *c);
 /* message of the last failed dg2ref_init */
 const char *dg2ref_init_error(void);
 void dg2ref_destroy(dg2ref_ctx *c);
-/* number of OpenMP threads the passes use */
+/* number of OpenMP threads the passes use; set it (n > 0) for the calling thread */
 int dg2ref_threads(void);
+void dg2ref_set_threads(int n);
 
 /* ---- pieces exposed for unit pins ---- */
 /* HLL flux across a face with normal n: states (h, u_n, u_t) left and right;

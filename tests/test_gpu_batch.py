@@ -86,7 +86,7 @@ def test_batch_run_lands_on_t_end_per_member(env):
     g = batched[2]
     P, Q = g.planes(), o.planes()
     H = max(np.abs(Q[0]).max(), 1e-3)
-    Qs = max(np.abs(Q[3]).max(), np.abs(Q[6]).max(), H * np.sqrt(9.80665 * H))
+    Qs = max(np.abs(Q[3]).max(), np.abs(Q[6]).max(), 1e-3)
     scale = np.array([H] * 3 + [Qs] * 6)
     err = max(np.abs(P[p] - Q[p]).max() / scale[p] for p in range(9))
     print(f"batched member vs oracle at t=5 s: {err:.2e}", flush=True)

@@ -15,6 +15,7 @@ bounded by the per-step rounding of the mean depths.
 import numpy as np
 import pytest
 
+import urban_window as UW
 from oracle import Oracle
 from paper_2107_02750_amd import scenarios as S
 
@@ -118,3 +119,46 @@ def test_fp32_mass_ledger_drift(dg2):
     print(f"FP32 datum mass drift {bal / scale:.2e} over {steps} steps", flush=True)
     # each step rounds every wet mean depth once per stage (<= 2^-24 relative)
     assert abs(bal) <= steps * 2 * 2.0 ** -24 * scale
+
+
+def test_fp32_urban_window_error_against_oracle(dg2):
+    """The precision form's terrain as configured: FP32 with bed datums and the FP64
+    oracle, both from the oracle's state at t = 300 s on a 2048 x 512 window (fronts at
+    every block wall), 100 steps each on their own time steps to the same end time;
+    the errors are printed (and recorded in the design notes)."""
+    base, cut, P = UW.state_at_t0()
+    full = np.zeros((9, base.ny, base.nx))
+    full[:, :, :UW.CUT] = P
+    gpu = dg2.DG2(base.replace(init_mode=S.MODE_PLANES, init_data=full, t0=UW.T0), dg2.FP32)
+    ref = Oracle(cut.replace(init_mode=S.MODE_PLANES, init_data=P, t0=UW.T0))
+    for _ in range(100):
+        ref.step()
+    t = ref.scalars()["t"]
+    gpu.run(t)
+    h = gpu.read(0).astype(np.float64)
+    assert not h[:, UW.CUT - 32:].any()
+    href = ref.read(0)
+    err = np.abs(h[:, :UW.CUT] - href)
+    wet = (href > 0) | (h[:, :UW.CUT] > 0)
+    rms = float(np.sqrt(np.mean(err[wet] ** 2)))
+    print(f"urban window t={t:.1f} s: FP32 datum vs FP64 oracle max depth error "
+          f"{err.max():.2e} m, RMS over wet cells {rms:.2e} m", flush=True)
+    assert err.max() <= 5e-2 and rms <= 1e-3
+
+
+def test_fp32_non_default_tile_against_oracle(dg2):
+    """The second FP32 tile shape against the FP64 oracle directly (as the default
+    shape in the test above)."""
+    sc = urban_small()
+    shape = dg2.tile_shapes(dg2.FP32)[1]
+    gpu = dg2.DG2(sc, dg2.FP32, tile=shape)
+    assert (gpu.kernel_info()["tile_x"], gpu.kernel_info()["tile_y"]) == tuple(shape)
+    ref = Oracle(sc)
+    for _ in range(40):
+        ref.step()
+    t = ref.scalars()["t"]
+    gpu.run(t)
+    err = np.abs(gpu.read(0).astype(np.float64) - ref.read(0))
+    print(f"urban, FP32 tile {shape}: max depth error {err.max():.2e} m", flush=True)
+    assert err.max() <= 5e-5
+    assert np.sqrt(np.mean(err ** 2)) <= 2e-6

@@ -28,23 +28,28 @@ def dg2():
     return mod
 
 
-def rel_err(gpu, ref):
+def rel_err(gpu, ref, still=False):
+    """Depth against max|h0|, discharges against max(max|qx0|, max|qy0|), each floored
+    at 1e-3 (m, m^2/s); in still water (exact discharge zero, round-off noise of about
+    1e-15 m^2/s on both sides) each side's discharge is compared with zero instead."""
     a, b = gpu.planes(), ref.planes()
     assert not a[[1, 2, 4, 5, 7, 8]].any(), "FV1 slope planes must stay zero"
     H = max(np.abs(b[0]).max(), 1e-3)
-    Q = max(np.abs(b[3]).max(), np.abs(b[6]).max(), H * np.sqrt(G * H))
+    if still:
+        return max(np.abs(a[0] - b[0]).max() / H, np.abs(a[[3, 6]]).max(), np.abs(b[[3, 6]]).max())
+    Q = max(np.abs(b[3]).max(), np.abs(b[6]).max(), 1e-3)
     return max(np.abs(a[0] - b[0]).max() / H, np.abs(a[3] - b[3]).max() / Q,
                np.abs(a[6] - b[6]).max() / Q)
 
 
-def run_pair(dg2, sc, steps, every=5):
+def run_pair(dg2, sc, steps, every=5, still=False):
     gpu, ref = dg2.DG2(sc, dg2.FP64), Oracle(sc)
     assert abs(gpu.next_dt() - ref.next_dt()) <= DT_TOL * ref.next_dt()
     for k in range(steps):
         a, b = gpu.step(), ref.step()
         assert abs(a - b) <= DT_TOL * b, (k, a, b)
         if (k + 1) % every == 0 or k + 1 == steps:
-            e = rel_err(gpu, ref)
+            e = rel_err(gpu, ref, still)
             assert e <= TOL, (sc.name, k + 1, e)
     return gpu, ref
 
@@ -67,7 +72,7 @@ def cases():
 def test_fv1_steps_match_oracle(dg2, idx):
     sc = cases()[idx].as_fv1()
     print(f"case {sc.name} {sc.nx}x{sc.ny}", flush=True)
-    gpu, ref = run_pair(dg2, sc, steps=30)
+    gpu, ref = run_pair(dg2, sc, steps=30, still=idx in (1, 2))
     if idx == 6:
         a, b = gpu.scalars(), ref.scalars()
         for k in ("mass", "mass_in", "mass_out", "mass_clip"):
