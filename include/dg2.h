@@ -298,6 +298,36 @@ int dg2_tape_backward(dg2_tape *tp, const double *dj_dh, double *grad_manning, d
 const char *dg2_tape_last_error(const dg2_tape *tp);
 void dg2_tape_destroy(dg2_tape *tp);
 
+/* ---- One step that allocates nothing ----------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): one DG2 step (the step of dg2_step,
+ * same kernels) from the 9-plane FP64 state u_in to u_out, with no context and no
+ * workspace. The scratch it needs (V^n and U^int, 18 planes, the control block, the
+ * ledger and the boundary tables) lives in a static device array of
+ * DG2_NOALLOC_SCRATCH_BYTES bytes that each GPU the library runs on holds until the
+ * process ends; grids whose scratch does not fit (about 460,000 cells) are rejected
+ * with DG2_E_ARG. It calls no hipMalloc or hipFree.
+ * cfg: as for dg2_init (precision must be DG2_FP64, scheme DG2; bed_datum ignored).
+ * zv: device, (ny+1)*(nx+1) vertex elevations; manning: device, nx*ny values, or NULL
+ * to use manning_scalar; bcs, n_bcs: boundary segments (host), as for dg2_init.
+ * u_in, u_out: device, 9 planes of nx*ny doubles each (layout of dg2_read), distinct
+ * buffers, both owned by the caller; u_in is not modified. t: the time of u_in; the
+ * step takes the CFL step of u_in, capped at dt_max (if > 0) and at t_end - t (pass
+ * INFINITY for no end). dt_used (host, may be NULL): with it the call waits for the
+ * step and reports the time step taken, and DG2_E_NUMERIC if the state holds a NaN or
+ * the time step fell below 1e-12 s; without it the call returns once the work is
+ * queued on hip_stream (a hipStream_t, borrowed). Every call on one GPU shares that
+ * GPU's scratch array, which keeps the last call's contents: calls that overlap in
+ * time on one GPU (other streams, other host threads) race and must be serialised by
+ * the caller. Errors: DG2_E_ARG, DG2_E_UNSUPPORTED, DG2_E_DEVICE, DG2_E_NUMERIC;
+ * dg2_noalloc_last_error() holds the message (per host thread). */
+#define DG2_NOALLOC_SCRATCH_BYTES (64u << 20)
+int dg2_step_noalloc(const dg2_config *cfg, const double *zv, const double *manning,
+                     double manning_scalar, const dg2_boundary *bcs, int32_t n_bcs,
+                     const double *u_in, double *u_out, double t, double dt_max, double t_end,
+                     double *dt_used, void *hip_stream);
+const char *dg2_noalloc_last_error(void);
+
 const char *dg2_last_error(const dg2_ctx *c);
 const char *dg2_init_error(void);
 

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1587,3 +1588,180 @@ void dg2_destroy(dg2_ctx* c) {
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------------
+// one step that allocates nothing: its scratch (V^n, U^int, control block, ledger,
+// boundary tables) lives in a static device array, one copy per GPU for the process
+// ---------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[DG2_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices];  // the array's device address on each GPU
+std::mutex g_scratch_mu;
+thread_local std::string g_noalloc_err;
+
+int noalloc_fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_noalloc_err = buf;
+  return code;
+}
+
+// the scratch array's address on the current device (looked up once per device, with
+// that device current; host code never passes the array's own name to a kernel)
+int scratch_on_current_device(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return noalloc_fail(DG2_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return noalloc_fail(DG2_E_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return noalloc_fail(DG2_E_DEVICE, "scratch address: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return DG2_OK;
+}
+
+template <typename R, typename S>
+struct NoAllocStages {
+  static int run(Params<R> p, dim3 grid, dim3 block, hipStream_t st) {
+    hipLaunchKernelGGL((dg2k::stage_kernel<R, S, 1>), grid, block, 0, st, p);
+    hipLaunchKernelGGL((dg2k::stage_kernel<R, S, 2>), grid, block, 0, st, p);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DG2_OK : noalloc_fail(DG2_E_DEVICE, "stage launch: %s", hipGetErrorString(e));
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int dg2_step_noalloc(const dg2_config* cfg, const double* zv, const double* manning,
+                     double manning_scalar, const dg2_boundary* bcs, int32_t n_bcs,
+                     const double* u_in, double* u_out, double t, double dt_max, double t_end,
+                     double* dt_used, void* hip_stream) {
+  g_noalloc_err.clear();
+  if (check_config(cfg)) return noalloc_fail(DG2_E_ARG, "bad grid size or tile shape");
+  const dg2_config& c = *cfg;
+  if (c.precision != DG2_FP64 || c.scheme != DG2_SCHEME_DG2)
+    return noalloc_fail(DG2_E_UNSUPPORTED, "the no-allocation step covers FP64 DG2 only");
+  if (!(c.dx > 0) || !(c.g > 0) || !(c.cfl > 0) || !(c.h_tol >= 0) || !(c.dt_dry > 0) ||
+      !std::isfinite(c.dx) || !std::isfinite(c.g) || !std::isfinite(t) || !(t_end > t))
+    return noalloc_fail(DG2_E_ARG, "bad scalar parameter or time");
+  for (int e = 0; e < 4; ++e)
+    if (c.edge_kind[e] != DG2_BC_TRANSMISSIVE && c.edge_kind[e] != DG2_BC_WALL)
+      return noalloc_fail(DG2_E_ARG, "edge default must be transmissive or wall");
+  if (!zv || !u_in || !u_out) return noalloc_fail(DG2_E_ARG, "null bed or state pointer");
+  if (u_in == u_out) return noalloc_fail(DG2_E_ARG, "u_in and u_out must not overlap");
+  if (!manning && !(manning_scalar >= 0 && std::isfinite(manning_scalar)))
+    return noalloc_fail(DG2_E_ARG, "bad Manning n");
+  std::vector<int> bface;
+  std::vector<Seg> segs;
+  std::vector<double> knots;
+  std::string why;
+  if (build_tables(c, bcs, n_bcs, bface, segs, knots, why)) return noalloc_fail(DG2_E_ARG, "%s", why.c_str());
+  const Layout L = layout(c);
+  const size_t n = (size_t)c.nx * c.ny;
+  // scratch layout (256-byte aligned sections)
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = up(off + bytes);
+    return o;
+  };
+  const size_t o_v = take(9 * n * sizeof(double)), o_ui = take(9 * n * sizeof(double));
+  const size_t o_ctrl = take(sizeof(Ctrl)), o_led = take((size_t)L.n_tiles * 4 * sizeof(double));
+  const size_t o_bf = take(bface.size() * sizeof(int)), o_seg = take(segs.size() * sizeof(Seg));
+  const size_t o_kn = take(knots.size() * sizeof(double));
+  if (off > (size_t)DG2_NOALLOC_SCRATCH_BYTES)
+    return noalloc_fail(DG2_E_ARG, "grid of %zu cells needs %zu bytes of scratch; the no-allocation step has %zu",
+                        n, off, (size_t)DG2_NOALLOC_SCRATCH_BYTES);
+  char* base = nullptr;
+  int rc = scratch_on_current_device(&base);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + o_ctrl);
+  double* ledger = reinterpret_cast<double*>(base + o_led);
+  hipError_t e = hipMemcpyAsync(base + o_bf, bface.data(), bface.size() * sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(base + o_seg, segs.data(), segs.size() * sizeof(Seg), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(base + o_kn, knots.data(), knots.size() * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return noalloc_fail(DG2_E_DEVICE, "boundary tables: %s", hipGetErrorString(e));
+  hipLaunchKernelGGL(dg2k::reset_ctrl_kernel, dim3(64), dim3(256), 0, st, ctrl, t, ledger, (long long)L.n_tiles * 4);
+  Params<double> p{};
+  p.uin = u_in;
+  p.vbuf = reinterpret_cast<double*>(base + o_v);
+  p.uout = u_out;
+  p.ui = reinterpret_cast<double*>(base + o_ui);
+  p.zv = zv;
+  p.datum = nullptr;
+  p.manning = manning;
+  p.bface = reinterpret_cast<const int*>(base + o_bf);
+  p.segs = reinterpret_cast<const Seg*>(base + o_seg);
+  p.knots = reinterpret_cast<const double*>(base + o_kn);
+  p.ctrl = ctrl;
+  p.ledger = ledger;
+  p.n = (long long)n;
+  p.nx = c.nx;
+  p.ny = c.ny;
+  p.tx = L.tx;
+  p.ty = L.ty;
+  p.tiles_x = L.tiles_x;
+  p.n_tiles = L.n_tiles;
+  p.per_xcd = L.per_xcd;
+  p.nsegs = n_bcs;
+  p.max_knots = DG2_MAX_KNOTS;
+  p.limiter = c.limiter;
+  p.parity = 0;
+  p.fv1 = 0;
+  p.dx = c.dx;
+  p.idx = 1.0 / c.dx;
+  p.g = c.g;
+  p.h_tol = c.h_tol;
+  p.n_scalar = manning_scalar;
+  p.dxd = c.dx;
+  p.gd = c.g;
+  p.cfl = c.cfl;
+  p.htd = c.h_tol;
+  p.dt_dry = c.dt_dry;
+  p.dt_max = dt_max;
+  p.t_end = t_end;
+  p.dt_fix = 0.0;
+  // the CFL candidate of U^n (as a context's first step takes it), then the two stages
+  {
+    long long blocks = ((long long)n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL((dg2k::dtc_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, st, p, u_in, t,
+                       &ctrl->dtc[0].s[0]);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return noalloc_fail(DG2_E_DEVICE, "launch: %s", hipGetErrorString(e));
+  rc = with_shape<double, NoAllocStages>(L.shape, p, dim3(L.grid), dim3(L.threads), st);
+  if (rc) return rc;
+  if (dt_used) {
+    struct Head {
+      double t[2], dt_used[2];
+      long long step[2];
+      int health;
+    } h{};
+    static_assert(offsetof(Ctrl, health) == offsetof(Head, health), "control block head");
+    e = hipMemcpyAsync(&h, ctrl, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return noalloc_fail(DG2_E_DEVICE, "read back: %s", hipGetErrorString(e));
+    if (h.health & 1) return noalloc_fail(DG2_E_NUMERIC, "NaN in the state");
+    if (h.health & 2) return noalloc_fail(DG2_E_NUMERIC, "CFL time step below 1e-12 s");
+    *dt_used = h.dt_used[0];
+  }
+  return DG2_OK;
+}
+
+const char* dg2_noalloc_last_error(void) { return g_noalloc_err.c_str(); }
+
+}  // extern "C"

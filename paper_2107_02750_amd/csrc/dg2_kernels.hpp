@@ -1560,6 +1560,28 @@ __global__ void convert_kernel(const double* __restrict__ src, R* __restrict__ d
   if (k < count) dst[k] = R(src[k]);
 }
 
+// a control block for a step with no history, starting at time t: every CFL slot
+// cleared, times and counters set, health cleared, and n_led ledger doubles zeroed
+// (a kernel rather than memsets, so that the clearing is an ordinary launch)
+__global__ void reset_ctrl_kernel(Ctrl* __restrict__ ctrl, double t, double* __restrict__ ledger,
+                                  long long n_led) {
+  const long long k0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  if (k0 == 0) {
+    ctrl->t[0] = ctrl->t[1] = t;
+    ctrl->dt_used[0] = ctrl->dt_used[1] = 0.0;
+    ctrl->step[0] = ctrl->step[1] = 0;
+    ctrl->health = 0;
+    ctrl->pad = 0;
+  }
+  constexpr long long NS = NSLOT * SLOT_STRIDE;
+  for (long long k = k0; k < 5 * NS; k += stride) {
+    Cand& c = k < 2 * NS ? ctrl->dtc[k / NS] : ctrl->dtr[(k - 2 * NS) / NS];
+    c.s[k % NS] = INF_BITS;
+  }
+  for (long long k = k0; k < n_led; k += stride) ledger[k] = 0.0;
+}
+
 // sets *bad when any of count values is negative or not finite (Manning n given in
 // device memory is checked before it replaces the plane)
 __global__ void check_nonneg_kernel(const double* __restrict__ src, long long count, int* bad) {

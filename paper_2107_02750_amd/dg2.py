@@ -28,6 +28,7 @@ SYMBOLS = ("dg2_workspace_size", "dg2_init", "dg2_step", "dg2_run", "dg2_read",
            "dg2_set_manning", "dg2_set_hydrograph", "dg2_knot_count", "dg2_tape_create",
            "dg2_tape_forward",
            "dg2_tape_backward", "dg2_tape_last_error", "dg2_tape_destroy",
+           "dg2_step_noalloc", "dg2_noalloc_last_error",
            "dg2_last_error", "dg2_init_error", "dg2_destroy")
 
 _dp = C.POINTER(C.c_double)
@@ -110,6 +111,10 @@ def load(path: str = LIB_PATH):
     lib.dg2_tape_last_error.restype = C.c_char_p
     lib.dg2_tape_destroy.argtypes = [vp]
     lib.dg2_tape_destroy.restype = None
+    lib.dg2_step_noalloc.argtypes = [C.POINTER(Config), vp, vp, C.c_double, C.POINTER(Boundary),
+                                     i32, vp, vp, C.c_double, C.c_double, C.c_double, _dp, vp]
+    lib.dg2_noalloc_last_error.argtypes = []
+    lib.dg2_noalloc_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -501,3 +506,31 @@ def gauge_run_function():
 
     return GaugeRun
 
+
+def step_noalloc(sc, zv, u_in, u_out, t: float, dt_max: float = 0.0,
+                 t_end: float = float("inf"), manning=None, stream=None, sync: bool = True):
+    """One FP64 DG2 step from the 9-plane state u_in to u_out through the entry point
+    that allocates nothing (dg2_step_noalloc): zv ((ny+1) x (nx+1)), manning (ny x nx,
+    or None for the scenario's scalar), u_in and u_out (9 x ny x nx) are float64 device
+    tensors owned by the caller; the grid, edges and boundary segments come from the
+    scenario. Returns the time step taken if sync, else None (nothing waits)."""
+    import torch
+    lib = load()
+    cfg = make_config(sc, FP64)
+    for a, count in ((zv, (sc.ny + 1) * (sc.nx + 1)), (u_in, 9 * sc.ny * sc.nx),
+                     (u_out, 9 * sc.ny * sc.nx)) + (() if manning is None else ((manning, sc.ny * sc.nx),)):
+        if not _is_device_tensor(a) or not a.is_contiguous():
+            raise DG2Error(E_ARG, "device tensors (contiguous) expected")
+        _check_device_f64(a, count)
+    arr, nb, keep = _boundaries(sc)
+    st = stream if stream is not None else torch.cuda.current_stream(u_in.device)
+    dt = C.c_double()
+    rc = lib.dg2_step_noalloc(C.byref(cfg), C.c_void_p(zv.data_ptr()),
+                              C.c_void_p(manning.data_ptr()) if manning is not None else None,
+                              float(sc.manning_scalar), arr, nb, C.c_void_p(u_in.data_ptr()),
+                              C.c_void_p(u_out.data_ptr()), float(t), float(dt_max), float(t_end),
+                              C.byref(dt) if sync else None, C.c_void_p(st.cuda_stream))
+    del keep
+    if rc != 0:
+        raise DG2Error(rc, lib.dg2_noalloc_last_error().decode())
+    return dt.value if sync else None
