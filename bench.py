@@ -84,7 +84,10 @@ def measured_traffic(summary, kernel):
     return 1024.0 * (k["fetch"] * sc["fetch"] + k["write"] * sc["write"])
 
 
-def timed_steps(sim, steps, min_seconds=1.0, min_windows=5, event_seconds=0.25):
+TIMING = {"min_seconds": 1.0, "event_seconds": 0.25}
+
+
+def timed_steps(sim, steps, min_seconds=None, min_windows=5, event_seconds=None):
     """Throughput and kernel durations of a simulation.
 
     Throughput: windows of exactly `steps` steps, each between two device
@@ -95,6 +98,12 @@ def timed_steps(sim, steps, min_seconds=1.0, min_windows=5, event_seconds=0.25):
     over further windows with every launch bracketed (at least event_seconds; an event
     record costs the stream a few microseconds, which the throughput leaves out)."""
     import torch
+    if min_seconds is None:
+        min_seconds = TIMING["min_seconds"]
+    if event_seconds is None:
+        event_seconds = TIMING["event_seconds"]
+    if min_seconds <= 0.0:
+        min_windows = 1
     wins = []
     while sum(wins) < min_seconds or len(wins) < min_windows:
         torch.cuda.synchronize()
@@ -104,8 +113,9 @@ def timed_steps(sim, steps, min_seconds=1.0, min_windows=5, event_seconds=0.25):
         torch.cuda.synchronize()
         wins.append(time.perf_counter() - t0)
     sim.set_timing(True)
-    t_ev = 0.0
-    while t_ev < event_seconds:
+    t_ev, first = 0.0, True
+    while first or t_ev < event_seconds:
+        first = False
         t0 = time.perf_counter()
         for _ in range(steps):
             sim.step(sync=False)
@@ -188,13 +198,13 @@ def adjoint_leg(dg2, S, n, steps, n_gauges=32):
     nz0 = np.array([sc.manning.reshape(-1)[zi.reshape(-1) == z][0] for z in range(16)])
     q0 = np.asarray(sc.boundaries[0].q_knots, dtype=np.float64)
 
-    def run(manning=None, q=None, record=True):
+    def run(manning=None, q=None, keep=False):
         sim = dg2.DG2(sc, dg2.FP64)
         if manning is not None:
             sim.set_manning(manning)
         if q is not None:
             sim.set_hydrograph(0, q)
-        tape = dg2.Tape(sim, dts, gi)
+        tape = dg2.Tape(sim, dts, gi, checkpoint_every=-1 if keep else 0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = tape.forward()
@@ -217,6 +227,15 @@ def adjoint_leg(dg2, S, n, steps, n_gauges=32):
     gm, gq, _ = tape.backward(2.0 * (h - href), len(q0))
     t_bwd = time.perf_counter() - t0
     gz = np.array([gm.reshape(-1)[zi.reshape(-1) == z].sum() for z in range(16)])
+    del tape, sim
+    # the same gradient with every step's stage states kept by the forward run (three
+    # states per step of HBM, no recomputation in the backward pass)
+    simk, tapek, hk, t_fwd_k = run(keep=True)
+    t0 = time.perf_counter()
+    gmk, gqk, _ = tapek.backward(2.0 * (hk - href), len(q0))
+    t_bwd_k = time.perf_counter() - t0
+    same = bool(np.array_equal(gmk, gm) and np.array_equal(gqk, gq) and np.array_equal(hk, h))
+    del tapek, simk
 
     def misfit(manning=None, q=None):
         return float(((run(manning=manning, q=q)[2] - href) ** 2).sum())
@@ -243,6 +262,12 @@ def adjoint_leg(dg2, S, n, steps, n_gauges=32):
             "seconds": {"forward_plain": t_plain, "forward_recorded": t_fwd, "adjoint": t_bwd},
             "adjoint_over_forward": t_bwd / t_plain,
             "gradient_over_forward": (t_fwd + t_bwd) / t_plain,
+            "keep_every_step": {
+                "seconds": {"forward_recorded": t_fwd_k, "adjoint": t_bwd_k},
+                "adjoint_over_forward": t_bwd_k / t_plain,
+                "gradient_over_forward": (t_fwd_k + t_bwd_k) / t_plain,
+                "device_bytes": 3 * (len(dts) + 1) * 9 * n * n * 8,
+                "bitwise_equal_to_checkpointed": same},
             "fd_checks": checks, "max_rel_diff_vs_fd": worst}
 
 
@@ -367,6 +392,10 @@ def main():
                     help="only the FV1 leg, as its own JSON line (for profiler runs)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint leg, as its own JSON line (for profiler runs)")
+    ap.add_argument("--min-seconds", type=float, default=1.0,
+                    help="timed windows repeat until this much has been timed (profiler runs: 0)")
+    ap.add_argument("--event-seconds", type=float, default=0.25,
+                    help="evented windows repeat until this much has run (profiler runs: 0)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -379,6 +408,7 @@ def main():
     import torch
     from paper_2107_02750_amd import dg2, scenarios as S
 
+    TIMING.update(min_seconds=args.min_seconds, event_seconds=args.event_seconds)
     if args.fv1_only:
         r = fv1_leg(dg2, S, args.n, args.steps, args.warmup)
         if args.calibrate_copy_mib:
@@ -405,6 +435,7 @@ def main():
     for _ in range(args.warmup):
         sim.step(sync=False)
     torch.cuda.synchronize()
+    TIMING.update(min_seconds=args.min_seconds, event_seconds=args.event_seconds)
     el, tm, n_windows = timed_steps(sim, args.steps)
     value = n_cells * args.steps / el
     ms1, ms2 = tm["ms_stage1"], tm["ms_stage2"]
@@ -512,7 +543,9 @@ def main():
         ad = out["adjoint"]
         print(f"[bench] adjoint {args.adjoint_n}^2 x {args.adjoint_steps} steps: forward "
               f"{ad['seconds']['forward_plain']:.3f} s, adjoint {ad['seconds']['adjoint']:.3f} s "
-              f"({ad['adjoint_over_forward']:.1f}x), max rel diff vs FD {ad['max_rel_diff_vs_fd']:.1e}",
+              f"({ad['adjoint_over_forward']:.1f}x; gradient {ad['gradient_over_forward']:.2f}x, keeping "
+              f"every step {ad['keep_every_step']['gradient_over_forward']:.2f}x), max rel diff vs FD "
+              f"{ad['max_rel_diff_vs_fd']:.1e}",
               file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
         print(f"[bench] CPU oracle {out['cpu_baseline']['value']:.4g} cell-updates/s on "

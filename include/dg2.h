@@ -153,20 +153,25 @@ int dg2_init(const dg2_config *cfg, const double *z_vertices, const double *mann
  */
 int dg2_step(dg2_ctx *c, double dt_max, double *dt_used);
 
-/* Step until t == t_end exactly (the last step is shortened). Waits for the GPU.
+/* Run the simulation to a simulated end time, as the paper's case studies run each
+ * scenario over a stated duration (Sect. 3.1-3.3): step until t == t_end exactly (the
+ * last step is shortened). Waits for the GPU.
  * *steps_taken (may be NULL) receives the number of steps. Errors: DG2_E_ARG if
  * t_end is before the current time, DG2_E_NUMERIC (state left at the failing step). */
 int dg2_run(dg2_ctx *c, double t_end, int64_t *steps_taken);
 
 /* Copy one field of the current state to dst (nx*ny values of the context's real type):
- * 0..8 the coefficient planes, 9 eta0 = h0 + z0, 10 u0 = qx0/h0, 11 v0 = qy0/h0 (0
+ * 0..8 the coefficient planes of eq 2 (mean, x-slope and y-slope coefficients of h, qx
+ * and qy), and the outputs the paper reports (Sect. 3: depth, velocity, water level):
+ * 9 eta0 = h0 + z0, 10 u0 = qx0/h0, 11 v0 = qy0/h0 (0
  * where h0 <= h_tol). dst is device memory if dst_is_device, else host memory. Waits
  * for the GPU. */
 int dg2_read(dg2_ctx *c, int32_t field, void *dst, int32_t dst_is_device);
 
 /* Time, step count, stored mass sum(h0) dx^2 (computed now, FP64) and the FP64 mass
- * ledger: boundary inflow, boundary outflow and mass added by clipping negative mean
- * depths, so that mass - mass(t0) == mass_in - mass_out + mass_clip up to round-off.
+ * ledger that the conservative form of eq 1 closes: boundary inflow, boundary outflow
+ * and mass added by clipping negative mean depths, so that
+ * mass - mass(t0) == mass_in - mass_out + mass_clip up to round-off.
  * Any pointer may be NULL. Waits for the GPU. */
 int dg2_get_scalars(dg2_ctx *c, double *t, int64_t *step, double *mass, double *mass_in,
                     double *mass_out, double *mass_clip);
@@ -270,7 +275,9 @@ int dg2_knot_count(const dg2_ctx *c, int32_t seg, int32_t *n_knots);
  * n_steps steps of a context with prescribed time steps dts[k] (the replayed
  * schedule: each step takes exactly dts[k]; choose them within the CFL bound, e.g.
  * from a previous run), keeping the state every checkpoint_every steps
- * (0: ceil(sqrt(n_steps))) and the depth h0 of n_gauges gauge cells (indices j*nx + i)
+ * (0: ceil(sqrt(n_steps)); -1: every step's stage states, V^n, U^int and U^{n+1},
+ * so that the backward pass recomputes nothing, at 3 states per step of device memory)
+ * and the depth h0 of n_gauges gauge cells (indices j*nx + i)
  * at every step, initial state included: dg2_tape_forward writes them to gauge_h,
  * (n_steps+1) x n_gauges doubles, host memory or device memory if dst_is_device. The
  * Manning plane and the hydrograph knots in effect at dg2_tape_forward are copied into
@@ -286,7 +293,8 @@ int dg2_knot_count(const dg2_ctx *c, int32_t seg, int32_t *n_knots);
  * no face-velocity cap binds; if the run leaves that regime the call fails with
  * DG2_E_UNSUPPORTED. The forward call advances the context like dg2_step; the tape
  * allocates its checkpoints and work buffers (device memory, about
- * (n_steps / checkpoint_every + checkpoint_every + 8) x 9 x nx x ny doubles) and frees
+ * (n_steps / checkpoint_every + 3 checkpoint_every + 8) x 9 x nx x ny doubles, or
+ * (3 n_steps + 9) x 9 x nx x ny with every step kept) and frees
  * them in dg2_tape_destroy. Errors: DG2_E_ARG (bad arguments), DG2_E_UNSUPPORTED (not
  * FP64, not DG2, limiter on, or outside the regime), DG2_E_DEVICE, DG2_E_NUMERIC. */
 typedef struct dg2_tape dg2_tape;

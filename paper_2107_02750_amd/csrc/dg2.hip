@@ -1230,6 +1230,7 @@ int dg2_set_hydrograph(dg2_ctx* c, int32_t seg, const double* q_knots) {
 struct dg2_tape {
   dg2_ctx* c;
   int n_steps, K, n_ckpt, ng;
+  bool keep_all;               // every step's states kept by the forward run (no recomputation)
   std::vector<double> dts, t;  // t[k]: time at the start of step k
   double* ckpt;                // n_ckpt states (9n each)
   double* seg;                 // K states U^n of the segment being reversed
@@ -1295,7 +1296,8 @@ Params<double> tape_params(dg2_tape* tp, int r, int k) {
   p.uin = tp->seg + r * m9;
   p.vbuf = tp->segV + r * m9;
   p.ui = tp->segI + r * m9;
-  p.uout = r + 1 < tp->K ? tp->seg + (r + 1) * m9 : nullptr;
+  // seg holds K states (K + 1 when every step is kept: the run's final state too)
+  p.uout = r + 1 < tp->K + (tp->keep_all ? 1 : 0) ? tp->seg + (r + 1) * m9 : nullptr;
   p.ctrl = tp->ctrl;
   p.ledger = tp->ledger;
   if (p.manning) p.manning = tp->man;  // the parameters the run was recorded with
@@ -1331,7 +1333,7 @@ int dg2_tape_create(dg2_ctx* c, int32_t n_steps, const double* dts, const int32_
   g_init_err.clear();
   if (!out) return DG2_E_ARG;
   *out = nullptr;
-  if (!c || n_steps < 1 || !dts || n_gauges < 0 || (n_gauges > 0 && !gauges) || checkpoint_every < 0) {
+  if (!c || n_steps < 1 || !dts || n_gauges < 0 || (n_gauges > 0 && !gauges) || checkpoint_every < -1) {
     g_init_err = "bad tape arguments";
     return DG2_E_ARG;
   }
@@ -1353,7 +1355,9 @@ int dg2_tape_create(dg2_ctx* c, int32_t n_steps, const double* dts, const int32_
   if (!tp) return DG2_E_ARG;
   tp->c = c;
   tp->n_steps = n_steps;
-  tp->K = checkpoint_every > 0 ? checkpoint_every : (int)std::ceil(std::sqrt((double)n_steps));
+  tp->keep_all = checkpoint_every == -1;
+  tp->K = tp->keep_all ? n_steps
+                       : checkpoint_every > 0 ? checkpoint_every : (int)std::ceil(std::sqrt((double)n_steps));
   tp->n_ckpt = (n_steps + tp->K - 1) / tp->K;
   tp->ng = n_gauges;
   tp->dts.assign(dts, dts + n_steps);
@@ -1362,7 +1366,7 @@ int dg2_tape_create(dg2_ctx* c, int32_t n_steps, const double* dts, const int32_
   const size_t nfs = 2 * ((size_t)c->cfg.nx + c->cfg.ny);  // boundary face slots
   hipError_t e = hipMalloc((void**)&tp->ckpt, st * tp->n_ckpt);
   for (double** b : {&tp->seg, &tp->segV, &tp->segI})
-    if (e == hipSuccess) e = hipMalloc((void**)b, st * tp->K);
+    if (e == hipSuccess) e = hipMalloc((void**)b, st * (tp->K + (tp->keep_all && b == &tp->seg ? 1 : 0)));
   for (double** b : {&tp->lam, &tp->nu2})
     if (e == hipSuccess) e = hipMalloc((void**)b, st);
   if (e == hipSuccess) e = hipMalloc((void**)&tp->gman, c->n * sizeof(double));
@@ -1418,18 +1422,57 @@ int dg2_tape_forward(dg2_tape* tp, double* gauge_h, int32_t dst_is_device) {
   const unsigned gb = (unsigned)((tp->ng + 63) / 64);
   auto cur = [&]() { return reinterpret_cast<double*>(c->ws + (c->parity ? c->L.u1 : c->L.u0)); };
   if (tp->ng > 0) hipLaunchKernelGGL(dg2k::gauge_read_kernel, dim3(gb), dim3(64), 0, c->stream, cur(), tp->gidx, tp->ng, tp->gh);
-  for (int k = 0; k < tp->n_steps; ++k) {
-    if (k % tp->K == 0)
-      THIPC(tp, hipMemcpyAsync(tp->ckpt + (size_t)(k / tp->K) * 9 * c->n, cur(), st, hipMemcpyDeviceToDevice, c->stream));
-    c->dt_fix = tp->dts[k];
-    rc = step_any(c, 0.0, INFINITY);
-    c->dt_fix = 0.0;
-    if (rc) return tfail(tp, rc, "%s", c->err.c_str());
-    if (tp->ng > 0)
-      hipLaunchKernelGGL(dg2k::gauge_read_kernel, dim3(gb), dim3(64), 0, c->stream, cur(), tp->gidx, tp->ng,
-                         tp->gh + (size_t)(k + 1) * tp->ng);
+  if (tp->keep_all) {
+    // the stage kernels write each step's V^n, U^int and U^{n+1} into the tape's own
+    // buffers (as the recomputation of the checkpointed mode does), with the tape's
+    // control block carrying the time and the context's ledger the boundary mass; the
+    // final state and time go back to the context afterwards
+    const size_t m9 = 9 * c->n;
+    {
+      dg2k::Ctrl ctrl{};
+      set_cands_inf(ctrl);
+      ctrl.step[0] = ctrl.step[1] = 0;
+      THIPC(tp, hipMemcpyAsync(tp->ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice, c->stream));
+      THIPC(tp, hipStreamSynchronize(c->stream));
+    }
+    THIPC(tp, hipMemcpyAsync(tp->seg, cur(), st, hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = tape_set_time(tp, 0))) return rc;
+    for (int k = 0; k < tp->n_steps && rc == DG2_OK; ++k) {
+      Params<double> p = tape_params(tp, k, k);
+      p.ledger = reinterpret_cast<double*>(c->ws + c->L.ledger);
+      rc = with_shape<double, TapeStage>(c->L.shape, tp, p, 1);
+      if (rc == DG2_OK) rc = with_shape<double, TapeStage>(c->L.shape, tp, p, 2);
+      if (rc == DG2_OK && tp->ng > 0)
+        hipLaunchKernelGGL(dg2k::gauge_read_kernel, dim3(gb), dim3(64), 0, c->stream, tp->seg + (size_t)(k + 1) * m9,
+                           tp->gidx, tp->ng, tp->gh + (size_t)(k + 1) * tp->ng);
+    }
+    if (rc) return rc;
+    THIPC(tp, hipGetLastError());
+    THIPC(tp, hipMemcpyAsync(cur(), tp->seg + (size_t)tp->n_steps * m9, st, hipMemcpyDeviceToDevice, c->stream));
+    int health = 0;
+    THIPC(tp, hipMemcpyAsync(&health, &tp->ctrl->health, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if ((rc = pull_ctrl(c))) return tfail(tp, rc, "%s", c->err.c_str());
+    if (health & 1) return tfail(tp, DG2_E_NUMERIC, "NaN in the state");
+    Ctrl ctrl = *c->h_ctrl;  // the context moves to the end of the run
+    ctrl.t[c->parity] = tp->t[tp->n_steps];
+    ctrl.step[c->parity] += tp->n_steps;
+    set_cands_inf(ctrl);
+    THIPC(tp, hipMemcpyAsync(c->ws + c->L.ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice, c->stream));
+    if ((rc = launch_dtc<double>(c, tp->t[tp->n_steps]))) return tfail(tp, rc, "%s", c->err.c_str());
+  } else {
+    for (int k = 0; k < tp->n_steps; ++k) {
+      if (k % tp->K == 0)
+        THIPC(tp, hipMemcpyAsync(tp->ckpt + (size_t)(k / tp->K) * 9 * c->n, cur(), st, hipMemcpyDeviceToDevice, c->stream));
+      c->dt_fix = tp->dts[k];
+      rc = step_any(c, 0.0, INFINITY);
+      c->dt_fix = 0.0;
+      if (rc) return tfail(tp, rc, "%s", c->err.c_str());
+      if (tp->ng > 0)
+        hipLaunchKernelGGL(dg2k::gauge_read_kernel, dim3(gb), dim3(64), 0, c->stream, cur(), tp->gidx, tp->ng,
+                           tp->gh + (size_t)(k + 1) * tp->ng);
+    }
+    THIPC(tp, hipGetLastError());
   }
-  THIPC(tp, hipGetLastError());
   if ((rc = pull_ctrl(c))) return tfail(tp, rc, "%s", c->err.c_str());
   if ((rc = check_health(c))) return tfail(tp, rc, "%s", c->err.c_str());
   if (gauge_h && tp->ng > 0) {
@@ -1477,9 +1520,12 @@ int dg2_tape_backward(dg2_tape* tp, const double* dj_dh, double* grad_manning, d
   for (int sgi = tp->n_ckpt - 1; sgi >= 0 && rc == DG2_OK; --sgi) {
     const int s0 = sgi * tp->K, s1 = std::min(tp->n_steps, s0 + tp->K);
     // recompute the segment from its checkpoint, keeping each step's V^n and U^int
-    THIPC(tp, hipMemcpyAsync(tp->seg, tp->ckpt + (size_t)sgi * m9, st, hipMemcpyDeviceToDevice, sm));
-    if ((rc = tape_set_time(tp, s0))) break;
-    for (int k = s0; k < s1 && rc == DG2_OK; ++k) rc = tape_step(tp, k - s0, k, k + 1 < s1);
+    // (with every step kept, the forward run left them in place)
+    if (!tp->keep_all) {
+      THIPC(tp, hipMemcpyAsync(tp->seg, tp->ckpt + (size_t)sgi * m9, st, hipMemcpyDeviceToDevice, sm));
+      if ((rc = tape_set_time(tp, s0))) break;
+      for (int k = s0; k < s1 && rc == DG2_OK; ++k) rc = tape_step(tp, k - s0, k, k + 1 < s1);
+    }
     for (int k = s1 - 1; k >= s0 && rc == DG2_OK; --k) {
       const size_t r = (size_t)(k - s0) * m9;
       const double dt = tp->dts[k];

@@ -388,6 +388,18 @@ __device__ __forceinline__ R zvat(const Params<R>& p, int iv, int jv, R dT) {
   return z;
 }
 
+// the same with the tile shape known at compile time (the kernels' own TX x TY tiles):
+// the tile index takes shifts and multiplies instead of integer divisions
+template <int TX, int TY, typename R>
+__device__ __forceinline__ R zvat_tile(const Params<R>& p, int iv, int jv, R dT) {
+  R z = p.zv[(unsigned)(jv * (p.nx + 1) + iv)];
+  if (sizeof(R) == 4 && p.datum) {
+    const int oi = iv < p.nx ? iv : p.nx - 1, oj = jv < p.ny ? jv : p.ny - 1;
+    z += p.datum[(oj / TY) * p.tiles_x + oi / TX] - dT;
+  }
+  return z;
+}
+
 // bed mean and slopes of cell (i, j) (eq 8; mean summed in diagonal pairs), in the frame
 // of the cell's tile datum
 template <typename R>
@@ -1284,7 +1296,7 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
   const R* __restrict__ qxin = p.uin + 3 * n;
   const R* __restrict__ qyin = p.uin + 6 * n;
   const R ht = p.h_tol, g = p.g;
-  const R dT = tile_datum(p, i0, j0);
+  const R dT = (sizeof(R) == 4 && p.datum) ? p.datum[tile] : R(0);
 
   // No vector memory operation is in flight when a tile body starts; the wait costs
   // nothing and keeps the wait-count analysis from carrying in the other body's loads.
@@ -1314,10 +1326,10 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     w.qx = qxin[kk];
     w.qy = qyin[kk];
     w.nm = p.manning ? p.manning[kk] : p.n_scalar;
-    w.sw = zvat(p, i, j, dT);
-    w.se = zvat(p, i + 1, j, dT);
-    w.nw = zvat(p, i, j + 1, dT);
-    w.ne = zvat(p, i + 1, j + 1, dT);
+    w.sw = zvat_tile<TX, TY>(p, i, j, dT);
+    w.se = zvat_tile<TX, TY>(p, i + 1, j, dT);
+    w.nw = zvat_tile<TX, TY>(p, i, j + 1, dT);
+    w.ne = zvat_tile<TX, TY>(p, i + 1, j + 1, dT);
   };
   const int ca = tid % TX + 1, cb = tid / TX + 1, cpos = cb * RX + ca;
   Raw w0, w1;

@@ -404,7 +404,9 @@ class Batch:
 
 class Tape:
     """A recorded forward run of a DG2 simulation (FP64, limiter off, fully wet) with
-    prescribed time steps, and the discrete adjoint of that run."""
+    prescribed time steps, and the discrete adjoint of that run. checkpoint_every:
+    0 for ceil(sqrt(n_steps)), k for every k steps (the backward pass recomputes each
+    segment once), -1 to keep every step's stage states (no recomputation)."""
 
     def __init__(self, sim: DG2, dts, gauges, checkpoint_every: int = 0):
         lib = load()

@@ -114,6 +114,15 @@ def test_adjoint_matches_reference_gradient(dg2):
     assert np.array_equal(tape2.forward(), hs)
     gm2, gq2, gu2 = tape2.backward(2.0 * (hs - href), len(sc.boundaries[0].q_knots))
     assert np.array_equal(gm2, gm) and np.array_equal(gq2, gq) and np.array_equal(gu2, gu)
+    # nor does keeping every step's states (no recomputation in the backward pass); the
+    # context ends where the checkpointed run left it and steps on from there alike
+    sim3 = dg2.DG2(sc, dg2.FP64)
+    tape3 = dg2.Tape(sim3, dts, gi, checkpoint_every=-1)
+    assert np.array_equal(tape3.forward(), hs)
+    gm3, gq3, gu3 = tape3.backward(2.0 * (hs - href), len(sc.boundaries[0].q_knots))
+    assert np.array_equal(gm3, gm) and np.array_equal(gq3, gq) and np.array_equal(gu3, gu)
+    assert sim3.get_state() == sim2.get_state()
+    assert sim3.step() == sim2.step() and sim3.planes().tobytes() == sim2.planes().tobytes()
 
 
 def test_adjoint_with_walls_and_a_fixed_segment(dg2):
