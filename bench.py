@@ -352,13 +352,16 @@ def batched(dg2, S, count, t_end):
         bal = s_["mass"] - s_["mass_in"] + s_["mass_out"] - s_["mass_clip"]  # dry start
         drift = max(drift, abs(bal) / max(s_["mass"], s_["mass_in"], 1e-300))
     seq_el = 0.0
+    slowest = 0.0
     equal = True
     for sc, sim in zip(scs, sims):
         one = dg2.DG2(sc, dg2.FP32, stream=stream, tile=tile)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         one.run(t_end)
-        seq_el += time.perf_counter() - t0
+        el_one = time.perf_counter() - t0
+        seq_el += el_one
+        slowest = max(slowest, el_one)
         equal = equal and one.get_state() == sim.get_state()
         del one
     return {"workload": f"{count} fBm channel scenarios, sides U{{256..1024}} (total "
@@ -369,6 +372,7 @@ def batched(dg2, S, count, t_end):
             "launch_pairs": pairs,
             "one_at_a_time": {"value": work / seq_el, "seconds": seq_el},
             "speedup": seq_el / el, "bitwise_equal_to_one_at_a_time": equal,
+            "slowest_member_alone_s": slowest,
             "tile": list(tile), "autotuner_ms_per_step": tuned["ms_per_step"],
             "max_mass_balance_rel": drift}
 
