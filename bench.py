@@ -126,6 +126,27 @@ def timed_steps(sim, steps, min_seconds=None, min_windows=5, event_seconds=None)
     return float(np.median(wins)), tm, len(wins)
 
 
+def copy_bandwidth(mib=1024, reps=20):
+    """Measured device copy rate (GB/s, bytes read plus bytes written): the median of
+    reps device-to-device copies of mib MiB, each timed with HIP events on the current
+    stream. It is the practical ceiling that the kernels' traffic is held against
+    beside the datasheet peak."""
+    import torch
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    return 2.0 * (mib << 20) / float(np.median(ts)) / 1e9
+
+
 def cpu_baseline(sc, budget_s):
     """The FP64 CPU oracle on this host, stepping the same workload until budget_s
     seconds have passed (at least one step) after two untimed steps, on all the
@@ -158,7 +179,7 @@ def cpu_baseline(sc, budget_s):
                           "sample": f"{steps1} further steps on one thread ({secs1:.1f} s)"})
 
 
-def fv1_leg(dg2, S, n, steps, warmup):
+def fv1_leg(dg2, S, n, steps, warmup, copy_gbs=None):
     """The FV1 scheme (one launch per step) on the same all-wet terrain, FP64 and FP32:
     cell-updates/s and the fraction of the HBM roofline. Algorithmic bytes per cell and
     step: the three means and one bed vertex read, the three means written."""
@@ -176,6 +197,7 @@ def fv1_leg(dg2, S, n, steps, warmup):
         out[tag] = {"value": n * n * steps / el, "unit": "cell-updates/s", "ms_per_launch": ms,
                     "algorithmic_bytes_per_launch": bytes_,
                     "roofline_frac": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "frac_of_copy": (bytes_ / (ms * 1e-3) / 1e9 / copy_gbs) if copy_gbs else None,
                     "traffic": measured_traffic(f"traffic_fv1_kernel_fbm_channel_wet_{n}", tag)}
     return out
 
@@ -414,7 +436,7 @@ def main():
 
     TIMING.update(min_seconds=args.min_seconds, event_seconds=args.event_seconds)
     if args.fv1_only:
-        r = fv1_leg(dg2, S, args.n, args.steps, args.warmup)
+        r = fv1_leg(dg2, S, args.n, args.steps, args.warmup, copy_bandwidth())
         if args.calibrate_copy_mib:
             a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device="cuda")
             torch.empty_like(a).copy_(a)
@@ -449,8 +471,9 @@ def main():
                for k, ms in (("stage1", ms1), ("stage2", ms2))}
     step_alg = stage_bytes("stage1", n_cells, 8) + stage_bytes("stage2", n_cells, 8)
     info = sim.kernel_info()
-    print(f"[bench] FP64 {value:.4g} cell-updates/s, stage1 {ms1:.4f} ms, stage2 {ms2:.4f} ms",
-          file=sys.stderr, flush=True)
+    copy_gbs = copy_bandwidth()
+    print(f"[bench] FP64 {value:.4g} cell-updates/s, stage1 {ms1:.4f} ms, stage2 {ms2:.4f} ms, "
+          f"device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
 
     if args.calibrate_copy_mib:
         a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device="cuda")
@@ -485,6 +508,9 @@ def main():
                      "algorithmic_bytes_per_launch": stage_bytes(dom, n_cells, 8),
                      "frac_per_kernel": frac_of,
                      "step_frac": step_alg / ((ms1 + ms2) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "copy_gbs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs,
+                     "step_frac_of_copy": step_alg / ((ms1 + ms2) * 1e-3) / 1e9 / copy_gbs,
                      "implementation_bytes_per_launch": {
                          k: stage_bytes(k, n_cells, 8, IMPL_VALUES) for k in ("stage1", "stage2")}},
     }
@@ -524,7 +550,7 @@ def main():
                                 "spin_up_steps": spin, "spin_up_s": spin_s}
         print(f"[bench] as configured {out['as_configured']['value']:.4g} cell-updates/s, "
               f"wet {wet:.4f}", file=sys.stderr, flush=True)
-        out["fv1"] = fv1_leg(dg2, S, args.n, args.steps, args.warmup)
+        out["fv1"] = fv1_leg(dg2, S, args.n, args.steps, args.warmup, copy_gbs)
         print(f"[bench] FV1 FP64 {out['fv1']['fp64']['value']:.4g} cell-updates/s "
               f"({out['fv1']['fp64']['roofline_frac']:.2f} of HBM roofline), FP32 "
               f"{out['fv1']['fp32']['value']:.4g}", file=sys.stderr, flush=True)
