@@ -26,7 +26,7 @@ constexpr size_t ALIGN = 256;
 size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t u0, u1, ui, zv, datum, man, bface, segs, knots, ctrl, ledger, scal, total;
+  size_t u0, u1, ui, zv, zc, datum, man, bface, segs, knots, ctrl, ledger, scal, total;
   int shape, tx, ty, threads, tiles_x, tiles_y, n_tiles, per_xcd, grid;
 };
 
@@ -89,6 +89,7 @@ Layout layout(const dg2_config& c) {
   L.u1 = take(9 * n * rs);
   L.ui = take(9 * n * rs);
   L.zv = take((size_t)(c.nx + 1) * (c.ny + 1) * rs);
+  L.zc = take(c.scheme == DG2_SCHEME_FV1 ? n * rs : 0);  // FV1: the cell bed means
   L.datum = take((size_t)L.n_tiles * rs);
   L.man = take(n * rs);
   L.bface = take((size_t)2 * (c.nx + c.ny) * sizeof(int));
@@ -183,6 +184,7 @@ Params<R> params(const dg2_ctx* c) {
   p.uout = p.vbuf;
   p.ui = reinterpret_cast<R*>(c->ws + L.ui);
   p.zv = reinterpret_cast<const R*>(c->ws + L.zv);
+  p.zc = c->fv1 ? reinterpret_cast<const R*>(c->ws + L.zc) : nullptr;
   p.datum = c->datum ? reinterpret_cast<const R*>(c->ws + L.datum) : nullptr;
   p.manning = c->has_manning ? reinterpret_cast<const R*>(c->ws + L.man) : nullptr;
   p.bface = reinterpret_cast<const int*>(c->ws + L.bface);
@@ -487,6 +489,11 @@ int init_device(dg2_ctx* c, const double* zv, const double* man, int mode, const
       if ((rc = conv(zv, nv, c->L.zv))) break;
     }
     if (man && (rc = conv(man, n, c->L.man))) break;
+    if (c->fv1) {  // FV1 reads each cell's bed mean, fixed for the run, from its own plane
+      const Params<R> pb = params<R>(c);
+      hipLaunchKernelGGL((dg2k::bedmean_kernel<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                         c->stream, pb, reinterpret_cast<R*>(c->ws + c->L.zc));
+    }
     if (mode != DG2_INIT_LEVEL) {
       size_t cnt = mode == DG2_INIT_PLANES ? 9 * n : (mode == DG2_INIT_MEANS ? 3 * n : 3 * nv);
       hipError_t e = hipMemcpyAsync(st, data, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream);

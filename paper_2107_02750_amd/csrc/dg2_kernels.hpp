@@ -97,6 +97,7 @@ struct Params {
                                // neither pointer is restrict
   R* __restrict__ ui;          // U^int out (stage 1)
   const R* __restrict__ zv;    // vertex bed (relative to the owner tile's datum if datum)
+  const R* __restrict__ zc;    // FV1: bed mean of each cell (eq 8) in its own tile's frame
   const R* __restrict__ datum; // per tile, whole metres (FP32 with a bed datum), or nullptr
   const R* __restrict__ manning;  // per cell, or nullptr
   const int* __restrict__ bface;  // boundary faces: W[ny], E[ny], S[nx], N[nx]
@@ -384,18 +385,6 @@ __device__ __forceinline__ R zvat(const Params<R>& p, int iv, int jv, R dT) {
   if (sizeof(R) == 4 && p.datum) {
     const int oi = iv < p.nx ? iv : p.nx - 1, oj = jv < p.ny ? jv : p.ny - 1;
     z += tile_datum(p, oi, oj) - dT;
-  }
-  return z;
-}
-
-// the same with the tile shape known at compile time (the kernels' own TX x TY tiles):
-// the tile index takes shifts and multiplies instead of integer divisions
-template <int TX, int TY, typename R>
-__device__ __forceinline__ R zvat_tile(const Params<R>& p, int iv, int jv, R dT) {
-  R z = p.zv[(unsigned)(jv * (p.nx + 1) + iv)];
-  if (sizeof(R) == 4 && p.datum) {
-    const int oi = iv < p.nx ? iv : p.nx - 1, oj = jv < p.ny ? jv : p.ny - 1;
-    z += p.datum[(oj / TY) * p.tiles_x + oi / TX] - dT;
   }
   return z;
 }
@@ -1304,7 +1293,7 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
 
   // ---- phase 1: the step's time step; the box depths and velocities (friction
   // applied) and bed means ----
-  // The step count and time, then the state, Manning coefficient and bed vertices of the
+  // The step count and time, then the state, Manning coefficient and bed mean of the
   // own cell and of the thread's halo item are all issued before any is waited on; the
   // ring candidate, whose slot the count picks, follows while they are in flight. (The
   // other two rings are not read: one takes this step's atomic minima, the other is
@@ -1313,9 +1302,11 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
   const long long k_ld = ctl->step[a];
   const double t_ld = ctl->t[a];
   struct Raw {
-    R h, qx, qy, nm, sw, se, nw, ne;
+    R h, qx, qy, nm, z;
   };
-  auto load_raw = [&](int ab, int bb, Raw& w) {  // box position (ab, bb)
+  // box position (ab, bb); a cell of another tile has its bed mean moved into this
+  // tile's datum frame (a whole number of metres: exact)
+  auto load_raw = [&](int ab, int bb, bool own, Raw& w) {
     int i = i0 - 1 + ab, j = j0 - 1 + bb;
     if (EDGE) {
       i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
@@ -1326,14 +1317,12 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     w.qx = qxin[kk];
     w.qy = qyin[kk];
     w.nm = p.manning ? p.manning[kk] : p.n_scalar;
-    w.sw = zvat_tile<TX, TY>(p, i, j, dT);
-    w.se = zvat_tile<TX, TY>(p, i + 1, j, dT);
-    w.nw = zvat_tile<TX, TY>(p, i, j + 1, dT);
-    w.ne = zvat_tile<TX, TY>(p, i + 1, j + 1, dT);
+    w.z = p.zc[kk];
+    if (sizeof(R) == 4 && p.datum && !own) w.z += p.datum[(j / TY) * p.tiles_x + i / TX] - dT;
   };
   const int ca = tid % TX + 1, cb = tid / TX + 1, cpos = cb * RX + ca;
   Raw w0, w1;
-  load_raw(ca, cb, w0);
+  load_raw(ca, cb, true, w0);
   int hab = 0, hbb = 0;
   const bool has_item = tid < NRING;
   if (has_item) {
@@ -1341,13 +1330,13 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     else if (tid < 2 * TY) { hab = TX + 1; hbb = tid - TY + 1; }
     else if (tid < 2 * TY + TX) { hab = tid - 2 * TY + 1; hbb = 0; }
     else { hab = tid - 2 * TY - TX + 1; hbb = TY + 1; }
-    load_raw(hab, hbb, w1);
+    load_raw(hab, hbb, false, w1);
   }
 
   // the step's time step from the ring slot of this step
   const long long k = uniform(k_ld);
   const double t = uniform(t_ld);
-  const double mm = cand_read(ctl->dtr[k % 3]);
+  const double mm = uniform(cand_read(ctl->dtr[k % 3]));
   double dt = (mm == __longlong_as_double((long long)INF_BITS)) ? p.dt_dry : p.cfl * mm;
   const double dt_cfl = dt;
   if (p.dt_max > 0.0 && p.dt_max < dt) dt = p.dt_max;
@@ -1356,6 +1345,8 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     dt = p.t_end - t;
     t_next = p.t_end;
   }
+  dt = uniform(dt);  // the same in every lane: held in scalar registers
+  t_next = uniform(t_next);
   if (!(dt > 0.0)) {  // past t_end: carry the state over
     if (active) {
       p.vbuf[ck] = w0.h;
@@ -1378,8 +1369,8 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
   }
   const R dtr = R(dt);
 
-  // friction, then the box cell's depth, velocities and bed mean (eq 8, diagonal pairs)
-  // to LDS; returns the cell's discharges after friction
+  // friction, then the box cell's depth, velocities and bed mean (eq 8, from the plane
+  // set up at initialisation) to LDS; returns the cell's discharges after friction
   auto publish = [&](int ab, int bb, const Raw& w, R& qx, R& qy) {
     qx = w.qx;
     qy = w.qy;
@@ -1394,7 +1385,7 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     sm.h[r] = w.h;
     sm.u[r] = w.h > ht ? qx * rr : R(0);
     sm.v[r] = w.h > ht ? qy * rr : R(0);
-    sm.z0[r] = R(0.25) * ((w.ne + w.sw) + (w.nw + w.se));
+    sm.z0[r] = w.z;
   };
   R qx0, qy0;
   publish(ca, cb, w0, qx0, qy0);
@@ -1543,8 +1534,10 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
   }
 }
 
+// FP32 is built for 8 waves per SIMD (it needs about 50 VGPRs; without the bound its
+// scalar registers alone would hold it to 7), FP64 for 7 (70 VGPRs)
 template <typename R, typename S>
-__global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
+__global__ __launch_bounds__(S::X * S::Y, sizeof(R) == 4 ? 8 : 7) void fv1_kernel(Params<R> p) {
   using SM = SmemFV1<R, S>;
   constexpr int TX = SM::TX, TY = SM::TY, NT = SM::NT;
   constexpr int NRING = 2 * (TX + TY);
@@ -1566,6 +1559,18 @@ __global__ __launch_bounds__(S::X * S::Y) void fv1_kernel(Params<R> p) {
 // ---------------------------------------------------------------------------------
 // set-up and diagnostics kernels
 // ---------------------------------------------------------------------------------
+// the bed mean of every cell (eq 8, as the stage kernels form it), in the frame of the
+// datum of the cell's own tile: the FV1 kernel's piecewise-constant bed
+template <typename R>
+__global__ void bedmean_kernel(Params<R> p, R* __restrict__ zc) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= p.n) return;
+  const int i = int(k % p.nx), j = int(k / p.nx);
+  R z0, z1x, z1y;
+  bed(p, i, j, z0, z1x, z1y);
+  zc[k] = z0;
+}
+
 template <typename R>
 __global__ void convert_kernel(const double* __restrict__ src, R* __restrict__ dst, long long count) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;

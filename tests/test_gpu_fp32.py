@@ -80,6 +80,43 @@ def test_fp32_datum_results_invariant_under_bed_shift(dg2, case):
     assert np.abs((eb - ea)[wet] - 1000.0).max() <= 1e-4
 
 
+@pytest.mark.parametrize("case", ["urban", "fbm_inflow"])
+def test_fv1_fp32_datum_invariant_under_bed_shift(dg2, case):
+    """FV1 (Sect. 2.1.2) in FP32 reads each cell's bed mean from a plane formed at set-up
+    in the frame of the cell's own tile datum and moves halo cells into the reading
+    tile's frame by whole metres: raising the bed by 1000 m changes no bit."""
+    sc = (urban_small() if case == "urban" else quantised_fbm()).as_fv1()
+    print(f"case fv1 {case} {sc.nx}x{sc.ny}", flush=True)
+    a = dg2.DG2(sc, dg2.FP32)
+    b = dg2.DG2(raised(sc, 1000.0), dg2.FP32)
+    for k in range(60):
+        assert a.step() == b.step(), k
+    assert np.array_equal(a.planes(), b.planes())
+    sa, sb = a.scalars(), b.scalars()
+    for key in ("mass", "mass_in", "mass_out", "mass_clip"):
+        assert sa[key] == sb[key], key
+
+
+@pytest.mark.parametrize("dz", [0.0, 1000.0])
+def test_fv1_fp32_datum_depth_error_vs_fp64_oracle(dg2, dz):
+    """FV1 in FP32 with bed datums against the FP64 oracle's FV1 on the urban blocks
+    (fronts at the block walls) and on a raised bed: the error is that of FP32 depth
+    arithmetic, as for DG2."""
+    sc = raised(urban_small(), dz).as_fv1()
+    ref = Oracle(sc)
+    gpu = dg2.DG2(sc, dg2.FP32)
+    for _ in range(80):
+        ref.step()
+    t = ref.scalars()["t"]
+    gpu.run(t)
+    assert abs(gpu.scalars()["t"] - t) <= 1e-9
+    err = np.abs(gpu.read(0).astype(np.float64) - ref.read(0))
+    print(f"FV1 urban +{dz} m, t={t:.2f} s: FP32 datum max depth error {err.max():.2e} m, "
+          f"rms {np.sqrt(np.mean(err ** 2)):.2e} m", flush=True)
+    assert err.max() <= 5e-5
+    assert np.sqrt(np.mean(err ** 2)) <= 2e-6
+
+
 def test_fp32_datum_lake_at_rest_high_bed(dg2):
     base = S.lake_at_rest()
     for dz in (0.0, 1500.0):
