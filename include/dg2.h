@@ -131,7 +131,9 @@ int dg2_workspace_size(const dg2_config *cfg, size_t *bytes);
 
 /* Create a context: validate the inputs on the host, copy them to the workspace on
  * `hip_stream` (a hipStream_t; NULL = the default stream), project the bed (eq 8) and
- * the initial state on the GPU, and compute the first CFL time step.
+ * the initial state on the GPU, and compute the first CFL time step. An FV1 context
+ * also forms every cell's bed mean (eq 8) once, into its workspace, as its
+ * piecewise-constant bed (Sect. 2.1.2).
  *  z_vertices: (nx+1)*(ny+1) host doubles, finite.
  *  manning: nx*ny host doubles >= 0, or NULL to use manning_scalar everywhere.
  *  init_mode / init_data / eta_level: see DG2_INIT_*; depths must be >= 0. Discharge
