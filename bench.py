@@ -150,7 +150,9 @@ def copy_bandwidth(mib=1024, reps=20):
 def cpu_baseline(sc, budget_s):
     """The FP64 CPU oracle on this host, stepping the same workload until budget_s
     seconds have passed (at least one step) after two untimed steps, on all the
-    threads OpenMP gives it; then the same on one thread for half that budget."""
+    threads OpenMP gives it; then the same on one thread for half that budget; then, on
+    all threads for half the budget, the terrain as configured from the oracle's stored
+    state at t = 3600 s (the GPU's as-configured leg times the same terrain)."""
     import oracle
 
     def rate(o, budget):
@@ -171,12 +173,29 @@ def cpu_baseline(sc, budget_s):
     oracle.set_threads(1)
     steps1, secs1 = rate(o, 0.5 * budget_s)
     oracle.set_threads(cores)
-    return dict(value=sc.nx * sc.ny * steps / secs, unit="cell-updates/s",
-                cores=cores, kind="oracle",
-                sample=f"{steps} FP64 oracle steps of the same {sc.nx}x{sc.ny} all-wet "
-                       f"workload ({secs:.1f} s)",
-                one_core={"value": sc.nx * sc.ny * steps1 / secs1, "cores": 1,
-                          "sample": f"{steps1} further steps on one thread ({secs1:.1f} s)"})
+    out = dict(value=sc.nx * sc.ny * steps / secs, unit="cell-updates/s",
+               cores=cores, kind="oracle",
+               sample=f"{steps} FP64 oracle steps of the same {sc.nx}x{sc.ny} all-wet "
+                      f"workload ({secs:.1f} s)",
+               one_core={"value": sc.nx * sc.ny * steps1 / secs1, "cores": 1,
+                         "sample": f"{steps1} further steps on one thread ({secs1:.1f} s)"})
+    # the terrain as configured (dry start, inflow), from the oracle's own stored state
+    # at t = 3600 s (written by tests/golden/make_snapshots.py, which runs the oracle only)
+    snap = os.path.join(ROOT, "tests", "golden", f"fbm_channel_{sc.nx}_t3600.npz")
+    if sc.nx == sc.ny and os.path.exists(snap):
+        from paper_2107_02750_amd import scenarios as S
+        d = np.load(snap)
+        P = np.zeros((9, sc.nx * sc.ny))
+        P[:, d["idx"]] = d["vals"]
+        cs = S.fbm_channel(n=sc.nx).replace(init_mode=S.MODE_PLANES,
+                                            init_data=P.reshape(9, sc.ny, sc.nx), t0=float(d["t"]))
+        oc = oracle.Oracle(cs)
+        oc.step()
+        stc, sec = rate(oc, 0.5 * budget_s)
+        out["as_configured"] = {"value": sc.nx * sc.ny * stc / sec, "cores": cores,
+                                "sample": f"{stc} oracle steps of the terrain as configured from "
+                                          f"its stored state at t=3600 s ({sec:.1f} s)"}
+    return out
 
 
 def fv1_leg(dg2, S, n, steps, warmup, copy_gbs=None):
@@ -578,8 +597,11 @@ def main():
               f"{ad['max_rel_diff_vs_fd']:.1e}",
               file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
-        print(f"[bench] CPU oracle {out['cpu_baseline']['value']:.4g} cell-updates/s on "
-              f"{out['cpu_baseline']['cores']} threads", file=sys.stderr, flush=True)
+        cb = out["cpu_baseline"]
+        print(f"[bench] CPU oracle {cb['value']:.4g} cell-updates/s on {cb['cores']} threads, "
+              f"{cb['one_core']['value']:.4g} on one"
+              + (f"; as configured {cb['as_configured']['value']:.4g}" if "as_configured" in cb else ""),
+              file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

@@ -28,3 +28,12 @@ def test_algorithmic_bytes_per_stage():
     assert (bench.stage_bytes("stage1", 1, 4) + bench.stage_bytes("stage2", 1, 4)) == 188
     # what the kernels move by design: V^n written by stage 1 and read by stage 2
     assert bench.stage_bytes("stage1", 1, 8, bench.IMPL_VALUES) == 224
+
+
+def test_cpu_baseline_reports_all_threads_and_one():
+    from paper_2107_02750_amd import scenarios as S
+    r = bench.cpu_baseline(S.fbm_channel_wet(n=48), 0.2)
+    assert r["kind"] == "oracle" and r["unit"] == "cell-updates/s"
+    assert r["value"] > 0 and r["cores"] >= 1
+    assert r["one_core"]["cores"] == 1 and r["one_core"]["value"] > 0
+    assert "as_configured" not in r  # no stored state for this grid size
