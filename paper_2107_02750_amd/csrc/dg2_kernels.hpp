@@ -583,23 +583,26 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   constexpr int NHALO = 2 * NRING + 4;  // halo items: first ring, second ring, corners
   // vertex (iv, jv) sits at box position (iv - i0 + 2, jv - j0 + 2); a clamped halo
   // cell only uses vertices of in-domain cells, which lie in the box
-  R zl[VITER];
+  // (FP32 with datums: the owner tile's datum is loaded beside the vertex and the shift
+  // to this tile's frame is applied only when the vertex goes to LDS, so that no load of
+  // the phase waits for another)
+  R zl[VITER], zd[VITER];
 #pragma unroll
   for (int k = 0; k < VITER; ++k) {
     const int r = tid + k * NT;
     zl[k] = R(0);
+    zd[k] = dT;
     if (r < VB) {
       int iv = i0 - 2 + r % VX, jv = j0 - 2 + r / VX;
       if (EDGE) {
         iv = iv < 0 ? 0 : (iv > nx ? nx : iv);
         jv = jv < 0 ? 0 : (jv > ny ? ny : jv);
       }
-      R z = p.zv[(unsigned)(jv * (nx + 1) + iv)];
-      if (sizeof(R) == 4 && p.datum) {  // to this tile's frame
-        const int oi = iv < nx ? iv : nx - 1, oj = jv < ny ? jv : ny - 1;
-        z += p.datum[(oj / TY) * p.tiles_x + oi / TX] - dT;
+      zl[k] = p.zv[(unsigned)(jv * (nx + 1) + iv)];
+      if (sizeof(R) == 4 && p.datum) {  // 32-bit unsigned index arithmetic (oi, oj >= 0)
+        const unsigned oi = iv < nx ? iv : nx - 1, oj = jv < ny ? jv : ny - 1;
+        zd[k] = p.datum[(oj / TY) * (unsigned)p.tiles_x + oi / TX];
       }
-      zl[k] = z;
     }
   }
   auto zb = [&](int iv, int jv) -> R { return sm.zv[(jv - j0 + 2) * VX + (iv - i0 + 2)]; };
@@ -726,7 +729,10 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   }
 #pragma unroll
   for (int k = 0; k < VITER; ++k)
-    if (tid + k * NT < VB) sm.zv[tid + k * NT] = zl[k];
+    if (tid + k * NT < VB) {
+      if (sizeof(R) == 4 && p.datum) sm.zv[tid + k * NT] = zl[k] + (zd[k] - dT);  // this tile's frame
+      else sm.zv[tid + k * NT] = zl[k];
+    }
   publish(tid % TX + 2, tid / TX + 2, 2, true, va, nma);
   if (has_item) publish(ha, hbb, hnp, hxd, vb, nmb);
   for (int h = tid + NT; h < NHALO; h += NT) {  // shapes with more halo items than threads
@@ -1302,10 +1308,11 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
   const long long k_ld = ctl->step[a];
   const double t_ld = ctl->t[a];
   struct Raw {
-    R h, qx, qy, nm, z;
+    R h, qx, qy, nm, z, zd;
   };
-  // box position (ab, bb); a cell of another tile has its bed mean moved into this
-  // tile's datum frame (a whole number of metres: exact)
+  // box position (ab, bb); a cell of another tile is moved into this tile's datum frame
+  // (a whole number of metres: exact) when published, so that its datum load waits for
+  // nothing here
   auto load_raw = [&](int ab, int bb, bool own, Raw& w) {
     int i = i0 - 1 + ab, j = j0 - 1 + bb;
     if (EDGE) {
@@ -1318,7 +1325,9 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     w.qy = qyin[kk];
     w.nm = p.manning ? p.manning[kk] : p.n_scalar;
     w.z = p.zc[kk];
-    if (sizeof(R) == 4 && p.datum && !own) w.z += p.datum[(j / TY) * p.tiles_x + i / TX] - dT;
+    w.zd = dT;
+    if (sizeof(R) == 4 && p.datum && !own)  // i, j >= 0 here
+      w.zd = p.datum[(unsigned)j / TY * (unsigned)p.tiles_x + (unsigned)i / TX];
   };
   const int ca = tid % TX + 1, cb = tid / TX + 1, cpos = cb * RX + ca;
   Raw w0, w1;
@@ -1371,7 +1380,7 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
 
   // friction, then the box cell's depth, velocities and bed mean (eq 8, from the plane
   // set up at initialisation) to LDS; returns the cell's discharges after friction
-  auto publish = [&](int ab, int bb, const Raw& w, R& qx, R& qy) {
+  auto publish = [&](int ab, int bb, bool own, const Raw& w, R& qx, R& qy) {
     qx = w.qx;
     qy = w.qy;
     if (w.nm > R(0)) {
@@ -1385,13 +1394,13 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     sm.h[r] = w.h;
     sm.u[r] = w.h > ht ? qx * rr : R(0);
     sm.v[r] = w.h > ht ? qy * rr : R(0);
-    sm.z0[r] = w.z;
+    sm.z0[r] = (sizeof(R) == 4 && p.datum && !own) ? w.z + (w.zd - dT) : w.z;
   };
   R qx0, qy0;
-  publish(ca, cb, w0, qx0, qy0);
+  publish(ca, cb, true, w0, qx0, qy0);
   if (has_item) {
     R qxr, qyr;
-    publish(hab, hbb, w1, qxr, qyr);
+    publish(hab, hbb, false, w1, qxr, qyr);
   }
   __syncthreads();
 
