@@ -119,6 +119,10 @@ struct dg2_ctx {
   double bed_max;      // largest |z - datum| a tile reads (absolute |z| without datums)
   bool has_manning;
   double manning_scalar;
+  // set by a tape around each recorded step: gauge depths written by stage 2
+  double* gauge_h = nullptr;
+  const int* gmap = nullptr;
+  const int* gnext = nullptr;
   int nsegs;
   int parity;          // state buffer holding the current U^n
   Ctrl* h_ctrl;        // pinned mirror of the control block
@@ -218,6 +222,11 @@ Params<R> params(const dg2_ctx* c) {
   p.dt_max = 0.0;
   p.t_end = INFINITY;
   p.dt_fix = c->dt_fix;
+  if constexpr (sizeof(R) == 8) {
+    p.gauge_h = c->gauge_h;
+    p.gmap = c->gmap;
+    p.gnext = c->gnext;
+  }
   return p;
 }
 
@@ -1447,11 +1456,13 @@ int dg2_tape_forward(dg2_tape* tp, double* gauge_h, int32_t dst_is_device) {
     for (int k = 0; k < tp->n_steps && rc == DG2_OK; ++k) {
       Params<double> p = tape_params(tp, k, k);
       p.ledger = reinterpret_cast<double*>(c->ws + c->L.ledger);
+      if (tp->ng > 0) {  // stage 2 writes the gauge depths after the step
+        p.gauge_h = tp->gh + (size_t)(k + 1) * tp->ng;
+        p.gmap = tp->gmap;
+        p.gnext = tp->gnext;
+      }
       rc = with_shape<double, TapeStage>(c->L.shape, tp, p, 1);
       if (rc == DG2_OK) rc = with_shape<double, TapeStage>(c->L.shape, tp, p, 2);
-      if (rc == DG2_OK && tp->ng > 0)
-        hipLaunchKernelGGL(dg2k::gauge_read_kernel, dim3(gb), dim3(64), 0, c->stream, tp->seg + (size_t)(k + 1) * m9,
-                           tp->gidx, tp->ng, tp->gh + (size_t)(k + 1) * tp->ng);
     }
     if (rc) return rc;
     THIPC(tp, hipGetLastError());
@@ -1471,12 +1482,16 @@ int dg2_tape_forward(dg2_tape* tp, double* gauge_h, int32_t dst_is_device) {
       if (k % tp->K == 0)
         THIPC(tp, hipMemcpyAsync(tp->ckpt + (size_t)(k / tp->K) * 9 * c->n, cur(), st, hipMemcpyDeviceToDevice, c->stream));
       c->dt_fix = tp->dts[k];
+      if (tp->ng > 0) {  // stage 2 writes the gauge depths after the step
+        c->gauge_h = tp->gh + (size_t)(k + 1) * tp->ng;
+        c->gmap = tp->gmap;
+        c->gnext = tp->gnext;
+      }
       rc = step_any(c, 0.0, INFINITY);
       c->dt_fix = 0.0;
+      c->gauge_h = nullptr;
+      c->gmap = c->gnext = nullptr;
       if (rc) return tfail(tp, rc, "%s", c->err.c_str());
-      if (tp->ng > 0)
-        hipLaunchKernelGGL(dg2k::gauge_read_kernel, dim3(gb), dim3(64), 0, c->stream, cur(), tp->gidx, tp->ng,
-                           tp->gh + (size_t)(k + 1) * tp->ng);
     }
     THIPC(tp, hipGetLastError());
   }

@@ -110,6 +110,11 @@ struct Params {
   R dx, idx, g, h_tol, n_scalar;  // idx = 1 / dx (rounded once, on the host)
   double dxd, gd, cfl, htd, dt_dry, dt_max, t_end;
   double dt_fix;               // > 0: the step takes exactly this dt (a replayed schedule)
+  // a recorded run (FP64 only): stage 2 writes the new mean depth of every gauge cell to
+  // gauge_h[g] (gmap: a cell's first gauge or -1; gnext: the next gauge of that cell)
+  double* gauge_h;
+  const int* gmap;
+  const int* gnext;
 };
 
 template <typename R> struct K;
@@ -1075,6 +1080,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
 #pragma unroll
     for (int q = 0; q < 9; ++q) vn[q] = (p.vbuf + q * n)[ck];
   }
+  const int gfirst = (STAGE == 2 && p.gauge_h && active) ? p.gmap[ck] : -1;
   __syncthreads();
 
   // ---- phase 3: L, the stage update, and the per-block reductions ----
@@ -1127,6 +1133,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
     } else {
 #pragma unroll
       for (int q = 0; q < 9; ++q) (p.uout + q * n)[ck] = u[q];
+      for (int g = gfirst; g >= 0; g = p.gnext[g]) p.gauge_h[g] = double(u[0]);
       my_dtc = cell_dtc(p, u[0], u[1], u[2], u[3], u[6]);
     }
   }
