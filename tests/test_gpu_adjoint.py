@@ -317,3 +317,25 @@ def test_backward_uses_the_parameters_it_was_recorded_with(dg2):
     print(f"backward after a second forward: zones {ez:.2e}", flush=True)
     assert ez <= 1e-7
     assert other.grad is None
+
+
+@pytest.mark.parametrize("keep", [0, -1])
+def test_recorded_gauge_depths_with_shared_cells(dg2, keep):
+    """Gauges that share a cell (the stage-2 kernel follows each cell's chain of gauges)
+    record the same depth, and every recorded row equals the state of a plain run after
+    that many steps; in both recording modes."""
+    sc = case()
+    dts = schedule(sc, 6)
+    c1, c2 = 7 * N + 3, (N // 2) * N + 1
+    gi = np.array([c1, c2, c1, c1, c2], dtype=np.int64)
+    sim = dg2.DG2(sc, dg2.FP64)
+    hs = dg2.Tape(sim, dts, gi, checkpoint_every=keep).forward()
+    assert hs.shape == (7, 5)
+    assert np.array_equal(hs[:, 0], hs[:, 2]) and np.array_equal(hs[:, 0], hs[:, 3])
+    assert np.array_equal(hs[:, 1], hs[:, 4])
+    plain = dg2.DG2(sc, dg2.FP64)
+    for k in range(7):
+        h = plain.read(0).reshape(-1)
+        assert hs[k, 0] == h[c1] and hs[k, 1] == h[c2], k
+        if k < 6:
+            plain.step(float(dts[k]))
