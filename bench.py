@@ -467,6 +467,10 @@ def main():
 
     if args.adjoint_only:
         r = adjoint_leg(dg2, S, args.adjoint_n, args.adjoint_steps)
+        if args.calibrate_copy_mib:
+            a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device="cuda")
+            torch.empty_like(a).copy_(a)
+            torch.cuda.synchronize()
         print(json.dumps({"metric": "adjoint time over forward time (gauge misfit gradients)",
                           "value": r["adjoint_over_forward"], "unit": "ratio", "adjoint": r}),
               flush=True)
