@@ -37,3 +37,30 @@ def test_cpu_baseline_reports_all_threads_and_one():
     assert r["value"] > 0 and r["cores"] >= 1
     assert r["one_core"]["cores"] == 1 and r["one_core"]["value"] > 0
     assert "as_configured" not in r  # no stored state for this grid size
+
+
+def test_counter_record_is_used_only_for_the_sources_it_was_taken_from(tmp_path, monkeypatch):
+    import json
+    (tmp_path / "profiles").mkdir()
+    rec = {"kernel_source_sha256": "abc", "copy_scale": {"fetch": 2.0, "write": 1.0},
+           "kib_per_dispatch": {"stage1": {"fetch": 10.0, "write": 4.0}}}
+    (tmp_path / "profiles" / "traffic_x.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abc")
+    assert bench.measured_traffic("traffic_x", "stage1") == 1024.0 * (10.0 * 2.0 + 4.0 * 1.0)
+    assert bench.measured_traffic("traffic_x", "stage2") is None
+    assert bench.measured_traffic("traffic_missing", "stage1") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "changed")
+    assert bench.measured_traffic("traffic_x", "stage1") is None
+
+
+def test_committed_counter_records_name_their_hashed_sources():
+    import json
+    for name in ("traffic_stage_kernels_fbm_channel_wet_1024_fp64", "traffic_fv1_kernel_fbm_channel_wet_1024"):
+        with open(os.path.join(ROOT, "profiles", name + ".json")) as fh:
+            rec = json.load(fh)
+        assert rec["hashed"] == ["paper_2107_02750_amd/csrc/dg2_kernels.hpp",
+                                 "paper_2107_02750_amd/csrc/dg2.hip",
+                                 "paper_2107_02750_amd/build.py"]
+        assert len(rec["kernel_source_sha256"]) == 64
+        assert os.path.exists(os.path.join(ROOT, "profiles", rec["summary"]))
