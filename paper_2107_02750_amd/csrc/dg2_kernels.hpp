@@ -157,7 +157,7 @@ __device__ __forceinline__ double fsqrt(double x) {
   r = __builtin_fma(-s, s, x);
   return __builtin_fma(r, h, s);
 }
-__device__ __forceinline__ float fsqrt(float x) { return x > 0.0f ? __builtin_sqrtf(x) : 0.0f; }
+__device__ __forceinline__ float fsqrt(float x) { return x > 0.0f ? __builtin_amdgcn_sqrtf(x) : 0.0f; }
 
 // 1/sqrt(x) for x > 0: with e = 1 - x y^2, x^(-1/2) = y (1 - e)^(-1/2)
 // = y (1 + e/2 + 3e^2/8 + ...); one third-order step from the hardware estimate
