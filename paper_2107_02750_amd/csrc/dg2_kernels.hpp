@@ -502,6 +502,12 @@ __device__ __forceinline__ double wave_sum(double x) {
   x += swizzle_xor<16>(x);
   return lane_value(x, 0) + lane_value(x, 32);
 }
+// the same, skipped when every lane holds zero (the sum is then exactly zero): the
+// ledger's clipped-mass and boundary terms are zero in most waves, and the swizzle chain
+// is five dependent LDS round trips
+__device__ __forceinline__ double wave_sum_sparse(double x) {
+  return __builtin_amdgcn_ballot_w64(x != 0.0) ? wave_sum(x) : 0.0;
+}
 __device__ __forceinline__ double dmin2(double a, double b) { return b < a ? b : a; }
 __device__ __forceinline__ double wave_min(double x) {
   x = dmin2(x, swizzle_xor<1>(x));
@@ -1141,11 +1147,11 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   // per-block reductions in a fixed order (deterministic); boundary-flux ledger terms
   // exist only in edge tiles
   const int lane = tid & 63, wv = tid >> 6;
-  const double r_clip = wave_sum(led_clip);
+  const double r_clip = wave_sum_sparse(led_clip);
   double r_in = 0.0, r_out = 0.0;
   if (EDGE) {
-    r_in = wave_sum(led_in);
-    r_out = wave_sum(led_out);
+    r_in = wave_sum_sparse(led_in);
+    r_out = wave_sum_sparse(led_out);
   }
   if (lane == 0) {
     sm.red[wv][0] = r_in;
@@ -1513,11 +1519,11 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
   }
   const int lane = tid & 63, wv = tid >> 6;
   // boundary-flux ledger terms exist only in edge tiles
-  const double r_clip = wave_sum(led_clip);
+  const double r_clip = wave_sum_sparse(led_clip);
   double r_in = 0.0, r_out = 0.0;
   if (EDGE) {
-    r_in = wave_sum(led_in);
-    r_out = wave_sum(led_out);
+    r_in = wave_sum_sparse(led_in);
+    r_out = wave_sum_sparse(led_out);
   }
   const double r_dt = wave_min(my_dtc);
   if (lane == 0) {
