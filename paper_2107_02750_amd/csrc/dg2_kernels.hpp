@@ -436,12 +436,18 @@ __device__ __forceinline__ void ghost(const Params<R>& p, int code, double t, bo
 // CFL candidate of one cell: min over directions of dx / (|u0| + sqrt(g hmax)) with
 // hmax the largest of the mean and the two face limits in that direction; +inf if dry
 template <typename R>
-__device__ __forceinline__ double cell_dtc(const Params<R>& p, R h0, R h1x, R h1y, R qx0, R qy0) {
+__device__ __forceinline__ R cell_dtc_r(const Params<R>& p, R h0, R h1x, R h1y, R qx0, R qy0) {
   const R r = frcp(fmaxr(h0, Tiny<R>::v));
   const R u = qx0 * r, v = qy0 * r;
   const R a = p.dx * frcp(dabs(u) + fsqrt(p.g * (h0 + K<R>::s3 * dabs(h1x))));
   const R b = p.dx * frcp(dabs(v) + fsqrt(p.g * (h0 + K<R>::s3 * dabs(h1y))));
-  return h0 > p.h_tol ? double(fminr(a, b)) : __longlong_as_double((long long)INF_BITS);
+  return h0 > p.h_tol ? fminr(a, b) : R(__builtin_huge_val());
+}
+// the same as a double (the widening is exact and keeps the order, so a minimum taken in
+// R and widened once equals the minimum of the widened candidates)
+template <typename R>
+__device__ __forceinline__ double cell_dtc(const Params<R>& p, R h0, R h1x, R h1y, R qx0, R qy0) {
+  return double(cell_dtc_r(p, h0, h1x, h1y, qx0, qy0));
 }
 
 // magnitude cap of a face-limit velocity component: the larger neighbouring mean
@@ -516,6 +522,22 @@ __device__ __forceinline__ double wave_min(double x) {
   x = dmin2(x, swizzle_xor<8>(x));
   x = dmin2(x, swizzle_xor<16>(x));
   return dmin2(lane_value(x, 0), lane_value(x, 32));
+}
+// FP32 kernels take their CFL minimum in float: one swizzle per step instead of two
+template <int XOR>
+__device__ __forceinline__ float swizzle_xor(float x) {
+  constexpr int pattern = (XOR << 10) | 0x1F;
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), pattern));
+}
+__device__ __forceinline__ float fmin2(float a, float b) { return b < a ? b : a; }
+__device__ __forceinline__ float wave_min(float x) {
+  x = fmin2(x, swizzle_xor<1>(x));
+  x = fmin2(x, swizzle_xor<2>(x));
+  x = fmin2(x, swizzle_xor<4>(x));
+  x = fmin2(x, swizzle_xor<8>(x));
+  x = fmin2(x, swizzle_xor<16>(x));
+  return fmin2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0)),
+               __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32)));
 }
 
 // lane k < NSLOT reads slot k (one memory round trip for all of them) and the wave
@@ -1090,7 +1112,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
   __syncthreads();
 
   // ---- phase 3: L, the stage update, and the per-block reductions ----
-  double my_dtc = __longlong_as_double((long long)INF_BITS);
+  R my_dtc = R(__builtin_huge_val());  // the cell's CFL candidate, reduced in R
   if (active) {
     const int xw = tb * (TX + 1) + ta, ys = tb * TX + ta;
     const R fw[3] = {sm.fx[0][xw], sm.fx[1][xw], sm.fx[2][xw]};
@@ -1140,7 +1162,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
 #pragma unroll
       for (int q = 0; q < 9; ++q) (p.uout + q * n)[ck] = u[q];
       for (int g = gfirst; g >= 0; g = p.gnext[g]) p.gauge_h[g] = double(u[0]);
-      my_dtc = cell_dtc(p, u[0], u[1], u[2], u[3], u[6]);
+      my_dtc = cell_dtc_r(p, u[0], u[1], u[2], u[3], u[6]);
     }
   }
 
@@ -1159,7 +1181,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
     sm.red[wv][2] = r_clip;
   }
   if (STAGE == 2) {
-    const double r_dt = wave_min(my_dtc);
+    const double r_dt = double(wave_min(my_dtc));
     if (lane == 0) sm.red[wv][3] = r_dt;
   }
   __syncthreads();
@@ -1495,7 +1517,7 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
   }
   if (EDGE && active && cj == ny - 1 && j0 + TY > ny) face(false, ny, ci, cpos + RX);  // cut tile
   __syncthreads();
-  double my_dtc = __longlong_as_double((long long)INF_BITS);
+  R my_dtc = R(__builtin_huge_val());  // the cell's CFL candidate, reduced in R
   double led_clip = 0.0;
   if (active) {
     R hN, zN, hS, zS;
@@ -1515,7 +1537,7 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     p.vbuf[ck] = u0;
     (p.vbuf + 3 * n)[ck] = u1;
     (p.vbuf + 6 * n)[ck] = u2;
-    my_dtc = cell_dtc(p, u0, R(0), R(0), u1, u2);
+    my_dtc = cell_dtc_r(p, u0, R(0), R(0), u1, u2);
   }
   const int lane = tid & 63, wv = tid >> 6;
   // boundary-flux ledger terms exist only in edge tiles
@@ -1525,7 +1547,7 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
     r_in = wave_sum_sparse(led_in);
     r_out = wave_sum_sparse(led_out);
   }
-  const double r_dt = wave_min(my_dtc);
+  const double r_dt = double(wave_min(my_dtc));
   if (lane == 0) {
     sm.red[wv][0] = r_in;
     sm.red[wv][1] = r_out;
