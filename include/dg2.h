@@ -125,8 +125,11 @@ typedef struct {
 typedef struct dg2_ctx dg2_ctx;
 
 /* Device workspace bytes a context with this configuration needs (256-byte aligned
- * base required). Errors: DG2_E_ARG for a NULL pointer, a grid below 1x1 or an unknown
- * precision. */
+ * base required): 29 planes of nx*ny values (three 9-plane states, the bed vertices,
+ * Manning n; FV1 one more, its bed means) plus per-tile and fixed-size tables.
+ * Errors: DG2_E_ARG for a NULL pointer, a grid below 1x1 or an unknown precision;
+ * DG2_E_UNSUPPORTED for a grid of more than 2^31 cells (cell indices are 32-bit) or a
+ * tile shape that is not built. */
 int dg2_workspace_size(const dg2_config *cfg, size_t *bytes);
 
 /* Create a context: validate the inputs on the host, copy them to the workspace on
@@ -142,7 +145,10 @@ int dg2_workspace_size(const dg2_config *cfg, size_t *bytes);
  *  d_workspace / ws_bytes: device memory of at least dg2_workspace_size bytes.
  * On success *out is the new context; on failure *out is NULL and nothing is kept.
  * Errors: DG2_E_ARG (bad sizes, non-finite or negative values, overlapping or
- * out-of-range segments, unsorted knots, small workspace), DG2_E_DEVICE. */
+ * out-of-range segments, unsorted knots, small workspace); DG2_E_UNSUPPORTED (as for
+ * dg2_workspace_size, or an FP32 bed whose relief around some tile reaches 2^20 m);
+ * DG2_E_DEVICE (a HIP call failed, including the temporary device buffer of up to
+ * 9*nx*ny doubles that stages the host inputs). */
 int dg2_init(const dg2_config *cfg, const double *z_vertices, const double *manning,
              double manning_scalar, int32_t init_mode, const double *init_data,
              double eta_level, const dg2_boundary *bcs, int32_t n_bcs, void *d_workspace,

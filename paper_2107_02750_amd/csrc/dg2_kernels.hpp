@@ -589,7 +589,8 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
 
   const int ci = i0 + tid % TX, cj = j0 + tid / TX;
   const bool active = !EDGE || (ci < nx && cj < ny);
-  const unsigned ck = (unsigned)(cj * nx + ci);
+  // unsigned: a cell past the grid's last row (inactive) may lie beyond INT_MAX
+  const unsigned ck = (unsigned)cj * (unsigned)nx + (unsigned)ci;
 
   // stage 2 needs V^n of the own cell only at the end; FP32 has the registers to
   // issue its loads now
@@ -631,7 +632,8 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
         iv = iv < 0 ? 0 : (iv > nx ? nx : iv);
         jv = jv < 0 ? 0 : (jv > ny ? ny : jv);
       }
-      zl[k] = p.zv[(unsigned)(jv * (nx + 1) + iv)];
+      // unsigned: a grid of 2^31 cells has more than INT_MAX vertices
+      zl[k] = p.zv[(unsigned)jv * (unsigned)(nx + 1) + (unsigned)iv];
       if (sizeof(R) == 4 && p.datum) {  // 32-bit unsigned index arithmetic (oi, oj >= 0)
         const unsigned oi = iv < nx ? iv : nx - 1, oj = jv < ny ? jv : ny - 1;
         zd[k] = p.datum[(oj / TY) * (unsigned)p.tiles_x + oi / TX];
@@ -646,7 +648,7 @@ __device__ __forceinline__ void stage_body(const Params<R>& p, Smem<R, S>& sm, c
       i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
       j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
     }
-    return (unsigned)(j * nx + i);
+    return (unsigned)j * (unsigned)nx + (unsigned)i;
   };
   // halo item h: its box position and friction points (npair: 0 centre only, 1 one
   // Gauss pair whose slopes are picked by xdir, -1 none)
@@ -1321,7 +1323,8 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
   const long long n = p.n;
   const int ci = i0 + tid % TX, cj = j0 + tid / TX;
   const bool active = !EDGE || (ci < nx && cj < ny);
-  const unsigned ck = (unsigned)(cj * nx + ci);
+  // unsigned: a cell past the grid's last row (inactive) may lie beyond INT_MAX
+  const unsigned ck = (unsigned)cj * (unsigned)nx + (unsigned)ci;
   const R* __restrict__ hin = p.uin;
   const R* __restrict__ qxin = p.uin + 3 * n;
   const R* __restrict__ qyin = p.uin + 6 * n;
@@ -1354,7 +1357,7 @@ __device__ __forceinline__ void fv1_body(const Params<R>& p, SmemFV1<R, S>& sm, 
       i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
       j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
     }
-    const unsigned kk = (unsigned)(j * nx + i);
+    const unsigned kk = (unsigned)j * (unsigned)nx + (unsigned)i;
     w.h = hin[kk];
     w.qx = qxin[kk];
     w.qy = qyin[kk];

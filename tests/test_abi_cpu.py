@@ -113,3 +113,18 @@ def test_tile_shapes_and_grid():
     with pytest.raises(dg2.DG2Error) as e:
         dg2.workspace_bytes(S.dam_break(), dg2.FP64, tile=(24, 8))
     assert e.value.code == dg2.E_UNSUPPORTED
+
+
+def test_grid_size_limit():
+    """Up to 2^31 cells are accepted (32-bit cell indices) and sized in 64-bit byte
+    counts; one more row is refused."""
+    lib = dg2.load()
+    for prec, rs in ((dg2.FP64, 8), (dg2.FP32, 4)):
+        cfg = dg2.make_config(S.dam_break(nx=20, ny=8), prec)
+        cfg.nx, cfg.ny = 65536, 32768
+        out = C.c_size_t()
+        assert lib.dg2_workspace_size(C.byref(cfg), C.byref(out)) == dg2.OK
+        n = 65536 * 32768
+        assert out.value >= 29 * n * rs and out.value < 29 * n * rs + (1 << 30)
+        cfg.ny = 32769
+        assert lib.dg2_workspace_size(C.byref(cfg), C.byref(out)) == dg2.E_UNSUPPORTED
