@@ -198,6 +198,34 @@ def cpu_baseline(sc, budget_s):
     return out
 
 
+def fp32_leg(dg2, S, n, steps, warmup, copy_gbs=None):
+    """The DG2 step in FP32 with per-tile bed datums on the all-wet terrain: cell-updates/s,
+    the stage kernels' HIP-event times and the step's fraction of the HBM roofline by
+    the FP32 algorithmic bytes (188 B per cell-step), with the counter traffic where a
+    record for the current kernel sources exists."""
+    import torch
+    sc = S.fbm_channel_wet(n=n)
+    n_cells = sc.nx * sc.ny
+    s32 = dg2.DG2(sc, dg2.FP32)
+    for _ in range(warmup):
+        s32.step(sync=False)
+    torch.cuda.synchronize()
+    el, tm, n_windows = timed_steps(s32, steps)
+    ms = {"stage1": tm["ms_stage1"], "stage2": tm["ms_stage2"]}
+    step_alg = stage_bytes("stage1", n_cells, 4) + stage_bytes("stage2", n_cells, 4)
+    rate = step_alg / ((ms["stage1"] + ms["stage2"]) * 1e-3) / 1e9
+    rec = f"traffic_stage_kernels_fbm_channel_wet_{n}_fp32"
+    info = s32.kernel_info()
+    out = {"value": n_cells * steps / el, "unit": "cell-updates/s", "windows": n_windows,
+           "tile": [info["tile_x"], info["tile_y"]], "ms_per_launch": ms,
+           "algorithmic_bytes_per_launch": {k: stage_bytes(k, n_cells, 4) for k in ms},
+           "step_frac": rate / HBM_PEAK_GBS,
+           "traffic": {k: measured_traffic(rec, k) for k in ms}}
+    if copy_gbs:
+        out["step_frac_of_copy"] = rate / copy_gbs
+    return out
+
+
 def fv1_leg(dg2, S, n, steps, warmup, copy_gbs=None):
     """The FV1 scheme (one launch per step) on the same all-wet terrain, FP64 and FP32:
     cell-updates/s and the fraction of the HBM roofline. Algorithmic bytes per cell and
@@ -435,6 +463,8 @@ def main():
                     help="only the FP64 timed region (for profiler runs)")
     ap.add_argument("--fv1-only", action="store_true",
                     help="only the FV1 leg, as its own JSON line (for profiler runs)")
+    ap.add_argument("--fp32-only", action="store_true",
+                    help="only the FP32 DG2 step on the all-wet terrain (profiler runs)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint leg, as its own JSON line (for profiler runs)")
     ap.add_argument("--min-seconds", type=float, default=1.0,
@@ -463,6 +493,16 @@ def main():
         print(json.dumps({"metric": "FV1 cell-updates/s (forward-Euler step, FP64)",
                           "value": r["fp64"]["value"], "unit": "cell-updates/s", "fv1": r}),
               flush=True)
+        return
+
+    if args.fp32_only:
+        r = fp32_leg(dg2, S, args.n, args.steps, args.warmup, copy_bandwidth())
+        if args.calibrate_copy_mib:
+            a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device="cuda")
+            torch.empty_like(a).copy_(a)
+            torch.cuda.synchronize()
+        print(json.dumps({"metric": "DG2 cell-updates/s (full RK2 step, FP32 with bed datums)",
+                          "value": r["value"], "unit": "cell-updates/s", "fp32": r}), flush=True)
         return
 
     if args.adjoint_only:
@@ -539,24 +579,17 @@ def main():
     }
     if not args.no_extras:
         # FP32 instantiation, same workload, and its depth error against FP64 at t = 60 s
-        s32 = dg2.DG2(sc, dg2.FP32)
-        for _ in range(args.warmup):
-            s32.step(sync=False)
-        torch.cuda.synchronize()
-        el32, tm32, _ = timed_steps(s32, args.steps)
+        out["fp32"] = fp32_leg(dg2, S, args.n, args.steps, args.warmup, copy_gbs)
         a64, a32 = dg2.DG2(sc, dg2.FP64), dg2.DG2(sc, dg2.FP32)
         a64.run(60.0)
         a32.run(60.0)
         h64 = a64.read(0)
         h32 = a32.read(0).astype(np.float64)
         d = h32 - h64
-        out["fp32"] = {"value": n_cells * args.steps / el32, "unit": "cell-updates/s",
-                       "ms_per_launch": {"stage1": tm32["ms_stage1"], "stage2": tm32["ms_stage2"]},
-                       "step_frac": (stage_bytes("stage1", n_cells, 4) + stage_bytes("stage2", n_cells, 4))
-                       / ((tm32["ms_stage1"] + tm32["ms_stage2"]) * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                       "max_depth_error_m": float(np.abs(d).max()),
-                       "rms_depth_error_m": float(np.sqrt(np.mean(d * d))),
-                       "error_at": "t=60 s vs the FP64 GPU path (held to the FP64 oracle at 1e-12 by the parity tests)"}
+        out["fp32"].update({
+            "max_depth_error_m": float(np.abs(d).max()),
+            "rms_depth_error_m": float(np.sqrt(np.mean(d * d))),
+            "error_at": "t=60 s vs the FP64 GPU path (held to the FP64 oracle at 1e-12 by the parity tests)"})
         print(f"[bench] FP32 {out['fp32']['value']:.4g} cell-updates/s, max depth err "
               f"{out['fp32']['max_depth_error_m']:.3g} m", file=sys.stderr, flush=True)
         # the terrain as configured: dry start, inflow hydrograph, snapshot at t = 3600 s

@@ -56,7 +56,11 @@ def test_counter_record_is_used_only_for_the_sources_it_was_taken_from(tmp_path,
 
 def test_committed_counter_records_name_their_hashed_sources():
     import json
-    for name in ("traffic_stage_kernels_fbm_channel_wet_1024_fp64", "traffic_fv1_kernel_fbm_channel_wet_1024"):
+    names = sorted(f[:-5] for f in os.listdir(os.path.join(ROOT, "profiles"))
+                   if f.startswith("traffic_") and f.endswith(".json"))
+    assert "traffic_stage_kernels_fbm_channel_wet_1024_fp64" in names
+    assert "traffic_fv1_kernel_fbm_channel_wet_1024" in names
+    for name in names:
         with open(os.path.join(ROOT, "profiles", name + ".json")) as fh:
             rec = json.load(fh)
         assert rec["hashed"] == ["paper_2107_02750_amd/csrc/dg2_kernels.hpp",
