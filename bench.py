@@ -147,12 +147,18 @@ def copy_bandwidth(mib=1024, reps=20):
     return 2.0 * (mib << 20) / float(np.median(ts)) / 1e9
 
 
-def cpu_baseline(sc, budget_s):
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def cpu_baseline(sc, budget_s, gpu_value=None):
     """The FP64 CPU oracle on this host, stepping the same workload until budget_s
     seconds have passed (at least one step) after two untimed steps, on all the
     threads OpenMP gives it; then the same on one thread for half that budget; then, on
     all threads for half the budget, the terrain as configured from the oracle's stored
-    state at t = 3600 s (the GPU's as-configured leg times the same terrain)."""
+    state at t = 3600 s (the GPU's as-configured leg times the same terrain). Last, the
+    method's operations per cell and step from one step of the oracle's operation-tally
+    build on the same workload (each face and cell computed once), and with the GPU's
+    rate the algorithmic FP64 flop rate that implies."""
     import oracle
 
     def rate(o, budget):
@@ -195,6 +201,19 @@ def cpu_baseline(sc, budget_s):
         out["as_configured"] = {"value": sc.nx * sc.ny * stc / sec, "cores": cores,
                                 "sample": f"{stc} oracle steps of the terrain as configured from "
                                           f"its stored state at t=3600 s ({sec:.1f} s)"}
+    ot = oracle.Oracle(sc, tallied=True)
+    ot.tally_reset()
+    ot.step()
+    per = {k: v / (sc.nx * sc.ny) for k, v in ot.tally_read().items()}
+    flops = per["add"] + per["mul"] + per["div"] + per["sqrt"] + per["cbrt"]
+    out["op_tally"] = {"per_cell_step": per, "flops_per_cell_step": flops,
+                       "counted": "add, subtract, multiply, divide, sqrt and cbrt one flop "
+                                  "each; min/max, abs and compares listed apart",
+                       "sample": f"one oracle step of the same {sc.nx}x{sc.ny} workload"}
+    if gpu_value:
+        tf = flops * gpu_value / 1e12
+        out["op_tally"].update(gpu_algorithmic_tflops=tf,
+                               frac_of_fp64_vector_peak=tf / FP64_VECTOR_PEAK_TFLOPS)
     return out
 
 
@@ -633,11 +652,13 @@ def main():
               f"every step {ad['keep_every_step']['gradient_over_forward']:.2f}x), max rel diff vs FD "
               f"{ad['max_rel_diff_vs_fd']:.1e}",
               file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget, gpu_value=value)
         cb = out["cpu_baseline"]
         print(f"[bench] CPU oracle {cb['value']:.4g} cell-updates/s on {cb['cores']} threads, "
               f"{cb['one_core']['value']:.4g} on one"
-              + (f"; as configured {cb['as_configured']['value']:.4g}" if "as_configured" in cb else ""),
+              + (f"; as configured {cb['as_configured']['value']:.4g}" if "as_configured" in cb else "")
+              + f"; {cb['op_tally']['flops_per_cell_step']:.0f} algorithmic flops per cell-step "
+              f"({cb['op_tally']['gpu_algorithmic_tflops']:.2f} TFLOP/s on the GPU)",
               file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 

@@ -34,17 +34,20 @@ class _Boundary(C.Structure):
                 ("h_b", C.c_double), ("u_b", C.c_double), ("v_b", C.c_double)]
 
 
-_lib = None
+TALLY_LIB_PATH = os.path.join(HERE, "libdg2ref_tally.so")
+TALLY_NAMES = ("add", "mul", "div", "sqrt", "cbrt", "minmax", "abs", "cmp")
+
+_libs = {}
 
 
-def load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
+def load(path: str = LIB_PATH):
+    """The oracle library (or, with TALLY_LIB_PATH, its operation-tally build)."""
+    if path in _libs:
+        return _libs[path]
+    if not os.path.exists(path):
         from . import build as _b
         _b.build()
-    lib = C.CDLL(LIB_PATH)
+    lib = C.CDLL(path)
     vp = C.c_void_p
     lib.dg2ref_init.argtypes = [C.POINTER(_Config), _dp, _dp, C.c_double, C.c_int32, _dp,
                                 C.c_double, C.POINTER(_Boundary), C.c_int32, C.POINTER(vp)]
@@ -76,7 +79,12 @@ def load():
     lib.dg2ref_set_threads.restype = None
     lib.dg2ref_limit.argtypes = [vp, _dp, _dp]
     lib.dg2ref_friction.argtypes = [vp, _dp, C.c_double, _dp]
-    _lib = lib
+    if path == TALLY_LIB_PATH:
+        lib.dg2ref_tally_read.argtypes = [C.POINTER(C.c_longlong)]
+        lib.dg2ref_tally_read.restype = None
+        lib.dg2ref_tally_reset.argtypes = []
+        lib.dg2ref_tally_reset.restype = None
+    _libs[path] = lib
     return lib
 
 
@@ -99,8 +107,9 @@ class Oracle:
 
     PLANES = ("h0", "h1x", "h1y", "qx0", "qx1x", "qx1y", "qy0", "qy1x", "qy1y")
 
-    def __init__(self, sc):
-        lib = load()
+    def __init__(self, sc, tallied: bool = False):
+        """tallied: run on the operation-tally build (tally_reset / tally_read)."""
+        lib = load(TALLY_LIB_PATH if tallied else LIB_PATH)
         self._lib = lib
         self.nx, self.ny = int(sc.nx), int(sc.ny)
         cfg = _Config(self.nx, self.ny, sc.dx, sc.g, sc.cfl, sc.h_tol, sc.dt_dry, sc.t0,
@@ -197,6 +206,16 @@ class Oracle:
         out = np.empty_like(st)
         self._check(self._lib.dg2ref_friction(self._h, _ptr(st), float(dt), _ptr(out)))
         return out
+
+    def tally_reset(self) -> None:
+        self._lib.dg2ref_tally_reset()
+
+    def tally_read(self) -> dict:
+        """Floating-point operations done since the last reset, by kind (tally build
+        only): add (with subtract), mul, div, sqrt, cbrt, min/max, abs, compare."""
+        out = (C.c_longlong * len(TALLY_NAMES))()
+        self._lib.dg2ref_tally_read(out)
+        return dict(zip(TALLY_NAMES, (int(v) for v in out)))
 
 
 def hll(g, hL, unL, utL, hR, unR, utR) -> np.ndarray:

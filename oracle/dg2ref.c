@@ -974,7 +974,9 @@ int dg2ref_init(const dg2ref_config *cfg, const double *zv, const double *mannin
   c->nx = cfg->nx;
   c->ny = cfg->ny;
   c->n = (size_t)cfg->nx * cfg->ny;
-  const size_t n = c->n, nv = (size_t)(cfg->nx + 1) * (cfg->ny + 1);
+  size_t n, nv;  /* assigned, not initialised: the earlier errors jump past them */
+  n = c->n;
+  nv = (size_t)(cfg->nx + 1) * (cfg->ny + 1);
   if (!finite_all(zv, nv)) BAD("non-finite bed elevation");
   c->zv = malloc(nv * sizeof(double));
   c->z0 = malloc(n * sizeof(double));
@@ -1012,7 +1014,8 @@ int dg2ref_init(const dg2ref_config *cfg, const double *zv, const double *mannin
     for (size_t k = 0; k < n; ++k) c->manning[k] = manning_scalar;
   }
   /* boundaries */
-  bface_t *edges[4] = {c->bw, c->be, c->bs, c->bn};
+  bface_t *edges[4];  /* assigned, not initialised: the set-up errors jump past it */
+  edges[0] = c->bw; edges[1] = c->be; edges[2] = c->bs; edges[3] = c->bn;
   for (int e = 0; e < 4; ++e)
     for (int f = 0; f < edge_len(c, e); ++f) { edges[e][f].kind = cfg->edge_kind[e]; edges[e][f].seg = -1; }
   if (n_bcs < 0 || (n_bcs > 0 && !bcs)) BAD("bad boundary list");
@@ -1048,7 +1051,8 @@ int dg2ref_init(const dg2ref_config *cfg, const double *zv, const double *mannin
     }
   }
   /* initial state (Sect. 2.1.4: flow coefficients are projected like the bed) */
-  double *U = c->U;
+  double *U;
+  U = c->U;
   if (init_mode == 0) {
     if (!init_data || !finite_all(init_data, 9 * n)) BAD("bad initial planes");
     memcpy(U, init_data, 9 * n * sizeof(double));
