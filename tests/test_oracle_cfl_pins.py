@@ -75,3 +75,20 @@ def test_dry_and_near_dry_cells_take_no_part():
     means[0, 5, 5] = 2.0 * sc.h_tol
     o = Oracle(thin.replace(init_data=means))
     assert o.next_dt() == pytest.approx(CR * 2.0 / np.sqrt(G * 2.0 * sc.h_tol), rel=1e-14)
+
+
+@pytest.mark.parametrize("h1x,h1y", [(0.12, 0.03), (-0.2, 0.15), (0.0, -0.25)])
+def test_sloped_depth_takes_the_largest_depth_of_the_reconstruction(h1x, h1y):
+    """Inside a cell the depth is the planar expansion of eq 2, h0 + sqrt(3) xi h1 for xi
+    in [-1, 1] along each direction: the fastest signal in the cell runs at the mean
+    velocity plus sqrt(g h) at the largest depth that expansion reaches, found here by
+    sampling it."""
+    nx, ny, h0, qx0, qy0 = 9, 7, 1.0, 0.5, -0.3
+    P = np.zeros((9, ny, nx))
+    P[0], P[1], P[2], P[3], P[6] = h0, h1x, h1y, qx0, qy0
+    zv = np.zeros((ny + 1, nx + 1))
+    o = Oracle(S.Scenario("sloped", nx, ny, 2.0, zv, S.MODE_PLANES, P))
+    xi = np.linspace(-1.0, 1.0, 2001)
+    speeds = [abs(q) / h0 + np.sqrt(G * (h0 + np.sqrt(3.0) * xi * h1).max())
+              for q, h1 in ((qx0, h1x), (qy0, h1y))]
+    assert o.next_dt() == pytest.approx(CR * 2.0 / max(speeds), rel=1e-14)
