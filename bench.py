@@ -484,6 +484,8 @@ def main():
                     help="only the FV1 leg, as its own JSON line (for profiler runs)")
     ap.add_argument("--fp32-only", action="store_true",
                     help="only the FP32 DG2 step on the all-wet terrain (profiler runs)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched-scenario leg (profiler runs)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint leg, as its own JSON line (for profiler runs)")
     ap.add_argument("--min-seconds", type=float, default=1.0,
@@ -522,6 +524,13 @@ def main():
             torch.cuda.synchronize()
         print(json.dumps({"metric": "DG2 cell-updates/s (full RK2 step, FP32 with bed datums)",
                           "value": r["value"], "unit": "cell-updates/s", "fp32": r}), flush=True)
+        return
+
+    if args.batched_only:
+        r = batched(dg2, S, args.batch_count, args.batch_t_end)
+        print(json.dumps({"metric": "batched scenarios, aggregate cell-updates/s (FP32)",
+                          "value": r["value"], "unit": "cell-updates/s", "batched": r}),
+              flush=True)
         return
 
     if args.adjoint_only:
