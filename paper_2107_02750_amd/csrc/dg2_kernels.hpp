@@ -1221,11 +1221,7 @@ __device__ __forceinline__ void stage_tile(const Params<R> p, const int tile) {
   const int i0 = (tile % p.tiles_x) * TX, j0 = (tile / p.tiles_x) * TY;
 
   __shared__ Smem<R, S> sm;
-  // FP32 runs every tile through the general body: one body instead of two (29 KB of
-  // stage-1 code instead of 47 KB) measured 3 % faster for both FP32 stages, while in
-  // FP64 the interior body, without clamps and boundary faces, is 3.6 % faster
-  const bool interior =
-      sizeof(R) == 8 && i0 >= 2 && j0 >= 2 && i0 + TX + 2 <= p.nx && j0 + TY + 2 <= p.ny;
+  const bool interior = i0 >= 2 && j0 >= 2 && i0 + TX + 2 <= p.nx && j0 + TY + 2 <= p.ny;
   if (interior)
     stage_body<R, S, STAGE, false>(p, sm, tile, i0, j0);
   else
