@@ -68,3 +68,25 @@ def test_committed_counter_records_name_their_hashed_sources():
                                  "paper_2107_02750_amd/build.py"]
         assert len(rec["kernel_source_sha256"]) == 64
         assert os.path.exists(os.path.join(ROOT, "profiles", rec["summary"]))
+
+
+def test_profile_commands_use_existing_bench_flags():
+    """Every bench.py command quoted in the committed rocprofv3 summaries uses only
+    options the bench accepts, so each summary can be made again as written."""
+    import re
+    import subprocess
+    import sys
+    helptext = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
+                              capture_output=True, text=True, check=True).stdout
+    known = set(re.findall(r"(--[a-z0-9-]+)", helptext))
+    seen = 0
+    for name in sorted(os.listdir(os.path.join(ROOT, "profiles"))):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(ROOT, "profiles", name)) as fh:
+            text = fh.read()
+        for cmd in re.findall(r"bench\.py([^`\n]*)", text):
+            for flag in re.findall(r"(--[a-z0-9-]+)", cmd):
+                assert flag in known, (name, flag)
+                seen += 1
+    assert seen > 10
