@@ -150,7 +150,7 @@ def copy_bandwidth(mib=1024, reps=20):
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
-def cpu_baseline(sc, budget_s, gpu_value=None):
+def cpu_baseline(sc, budget_s, gpu_value=None, fv1_values=None):
     """The FP64 CPU oracle on this host, stepping the same workload until budget_s
     seconds have passed (at least one step) after two untimed steps, on all the
     threads OpenMP gives it; then the same on one thread for half that budget; then, on
@@ -158,7 +158,8 @@ def cpu_baseline(sc, budget_s, gpu_value=None):
     state at t = 3600 s (the GPU's as-configured leg times the same terrain). Last, the
     method's operations per cell and step from one step of the oracle's operation-tally
     build on the same workload (each face and cell computed once), and with the GPU's
-    rate the algorithmic FP64 flop rate that implies."""
+    rate the algorithmic FP64 flop rate that implies; the same for one FV1 step, with the
+    GPU's FV1 rates (FP64, FP32) when given."""
     import oracle
 
     def rate(o, budget):
@@ -214,6 +215,15 @@ def cpu_baseline(sc, budget_s, gpu_value=None):
         tf = flops * gpu_value / 1e12
         out["op_tally"].update(gpu_algorithmic_tflops=tf,
                                frac_of_fp64_vector_peak=tf / FP64_VECTOR_PEAK_TFLOPS)
+    of = oracle.Oracle(sc.as_fv1(), tallied=True)
+    of.tally_reset()
+    of.step()
+    per = {k: v / (sc.nx * sc.ny) for k, v in of.tally_read().items()}
+    flops = per["add"] + per["mul"] + per["div"] + per["sqrt"] + per["cbrt"]
+    out["op_tally_fv1"] = {"per_cell_step": per, "flops_per_cell_step": flops,
+                           "sample": f"one oracle FV1 step of the same {sc.nx}x{sc.ny} workload"}
+    for prec, v in (fv1_values or {}).items():
+        out["op_tally_fv1"][f"gpu_algorithmic_tflops_{prec}"] = flops * v / 1e12
     return out
 
 
@@ -661,7 +671,10 @@ def main():
               f"every step {ad['keep_every_step']['gradient_over_forward']:.2f}x), max rel diff vs FD "
               f"{ad['max_rel_diff_vs_fd']:.1e}",
               file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget, gpu_value=value)
+        fv1_values = ({k: out["fv1"][k]["value"] for k in ("fp64", "fp32")}
+                      if "fv1" in out else None)
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget, gpu_value=value,
+                                           fv1_values=fv1_values)
         cb = out["cpu_baseline"]
         print(f"[bench] CPU oracle {cb['value']:.4g} cell-updates/s on {cb['cores']} threads, "
               f"{cb['one_core']['value']:.4g} on one"
